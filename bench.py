@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the cumulant hot path on one MI355X.
+
+A step is one call of cum_cumulants on resident device data: FP64 centring,
+the block moment contraction of every order 2..d_max, the fixed-order FP64
+chunk reduction and the cumulant recursion.  ``value`` is the effective
+throughput of the mixed-precision path,
+    algorithmic FLOP = sum_{d=2}^{d_max} 2 * t * stored_d
+(one multiply-add per stored block entry per sample, the work of the block
+method) divided by the measured step time.  The FP64 path and any further
+precisions are timed on the same data and reported beside it, each with its
+per-order relative error against the FP64 CPU oracle on sampled entries.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cumulants d=4..6: eff. TFLOP/s + MFMA util, FP64 vs mixed at stated rel error"
+# MI355X dense matrix-core peaks, TFLOP/s
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "bf16x3": 2500.0}
+# matrix-core products issued per algorithmic multiply-add
+PRODUCTS = {"f64": 1, "f32": 1, "bf16x2": 4, "bf16x3": 6}
+DTYPE = {"f64": "f64", "f32": "f32", "bf16x2": "bf16x2(f32 acc)", "bf16x3": "bf16x3(f32 acc)"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_flops(pc, t, n, d_max, b):
+    return sum(2.0 * t * pc.layout(n, d, b)["elems"] for d in range(2, d_max + 1))
+
+
+def time_path(torch, pc, Xd, d_max, b, prec, steps, warmup):
+    t, n = Xd.shape
+    out = {d: torch.empty(pc.layout(n, d, b)["elems"], dtype=torch.float64, device="cuda")
+           for d in range(2, d_max + 1)}
+    ws = torch.empty(pc.workspace_size(t, n, d_max, b, prec), dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        pc.cumulants(Xd, d_max, b, prec, ws=ws, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pc.cumulants(Xd, d_max, b, prec, ws=ws, out=out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    # second pass: the same calls with every launch bracketed by HIP events
+    pc.timing_enable(True)
+    pc.timing_read()
+    for _ in range(steps):
+        pc.cumulants(Xd, d_max, b, prec, ws=ws, out=out)
+    kinds = pc.timing_read()
+    pc.timing_enable(False)
+    torch.cuda.synchronize()
+    return wall, kinds, out
+
+
+def sampled_errors(orc, pc, X, kappa, n, d_max, b, count=300, seed=7):
+    """e_d = max |gpu - oracle| / max |oracle| over sampled stored entries
+    (random positions plus every pure-diagonal entry)."""
+    _, Xc = orc.center(X)
+    errs = {}
+    rng = np.random.default_rng(seed)
+    for d in range(2, d_max + 1):
+        elems = pc.layout(n, d, b)["elems"]
+        offs = rng.choice(elems, size=min(count, elems), replace=False)
+        diag = [pc.stored_offset(n, d, b, [i] * d) for i in range(n)]
+        offs = np.unique(np.concatenate([offs, diag]))
+        idx = orc.block_indices(n, d, b, offs)
+        keep = idx[:, 0] >= 0
+        offs, idx = offs[keep], idx[keep]
+        want = orc.cumulant_at(Xc, idx)
+        got = {p: k[d][offs] for p, k in kappa.items()}
+        den = np.abs(want).max()
+        errs[d] = {p: float(np.abs(g - want).max() / den) for p, g in got.items()}
+    return errs
+
+
+def cpu_baseline(orc, X, n, d_max, b, pc, target_s):
+    """The FP64 oracle (dense over all n^d entries) on the first ts samples,
+    ts sized for about target_s seconds; reported in the benchmark's unit."""
+    ts = 64
+    t0 = time.perf_counter()
+    orc.cumulants_dense(X[:ts], d_max)
+    dt = time.perf_counter() - t0
+    ts = int(min(len(X), max(64, ts * target_s / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    orc.cumulants_dense(X[:ts], d_max)
+    dt = time.perf_counter() - t0
+    flops = alg_flops(pc, ts, n, d_max, b)
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": orc.max_threads(), "kind": "oracle",
+            "sample": f"first {ts} of {len(X)} samples, dense FP64 oracle over all n^d entries of orders 2..{d_max}, "
+                      f"{dt:.1f} s; effective FLOP counted as for the GPU (2 t sum_d stored_d)",
+            "seconds": dt}
+
+
+def traffic_record(prec, workload):
+    """HBM bytes per moment launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"moment_kernel_{prec}_{workload}.pmc.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1701_05420_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("kernels_hip_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="t-gamma-mix-n48-t100000")
+    ap.add_argument("--prec", default="f32", help="precision of the reported path")
+    ap.add_argument("--compare", default="f64,bf16x3,bf16x2", help="further precisions timed on the same data")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-errors", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the path runs on a single MI355X (sharding across GPUs "
+              "is described in DESIGN.md but not built); run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1701_05420_amd as pc
+    import workloads
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    w = workloads.WORKLOADS[args.workload]
+    if w["t"] is None:
+        print("the batched workload is measured by --workload of a single dataset; see tests", file=sys.stderr)
+        sys.exit(2)
+    n, b, d_max, t = w["n"], w["b"], w["d_max"], w["t"]
+    log(f"workload {args.workload}: n={n} b={b} d_max={d_max} t={t}")
+    X = workloads.generate(args.workload)
+    Xd = torch.from_numpy(X).cuda()
+    flops = alg_flops(pc, t, n, d_max, b)
+
+    precs = [args.prec] + [p for p in args.compare.split(",") if p and p != args.prec]
+    res, kappa = {}, {}
+    for p in precs:
+        log(f"timing {p}")
+        wall, kinds, out = time_path(torch, pc, Xd, d_max, b, p, args.steps, args.warmup)
+        mom_ms, mom_n = kinds["moment"]
+        per_launch = mom_ms / max(mom_n, 1)
+        achieved = flops / (per_launch * 1e-3) / 1e12
+        res[p] = {"ms_per_step": wall * 1e3, "tflops": flops / wall / 1e12,
+                  "moment_ms_per_launch": per_launch, "moment_tflops": achieved,
+                  "mfma_frac": achieved * PRODUCTS[p] / PEAK[p],
+                  "kernel_ms": {k: v[0] / args.steps for k, v in kinds.items() if v[1]}}
+        kappa[p] = {d: out[d].cpu().numpy() for d in out}
+        log(f"  {p}: {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s; "
+            f"moment kernel {per_launch:.3f} ms = {achieved:.2f} TFLOP/s")
+
+    import oracle as orc
+
+    orc.build()
+    errs = {} if args.no_errors else sampled_errors(orc, pc, X, kappa, n, d_max, b)
+    main_p = args.prec
+    r = res[main_p]
+    roof = {"bound": "mfma", "achieved": r["moment_tflops"] * PRODUCTS[main_p], "peak": PEAK[main_p],
+            "unit": "TFLOP/s", "frac": r["moment_tflops"] * PRODUCTS[main_p] / PEAK[main_p],
+            "traffic": traffic_record(main_p, args.workload),
+            "kernel": "moment_kernel", "algorithmic_tflops": r["moment_tflops"],
+            "ms_per_launch": r["moment_ms_per_launch"]}
+    line = {
+        "metric": METRIC,
+        "value": r["tflops"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[main_p],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "b": b, "d_max": d_max, "t": t, "prec": main_p,
+                   "alg_flop_per_step": flops},
+        "roofline": roof,
+        "paths": {p: {k: v for k, v in res[p].items()} for p in precs},
+        "rel_err": {str(d): errs[d] for d in errs},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(orc, X, n, d_max, b, pc, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * cumulants.h -- C ABI of the MI355X (gfx950) moment and cumulant tensor
+ * library.
+ *
+ * Method: Domino, Gawron, Pawela, "Efficient computation of higher order
+ * cumulant tensors".  The library computes
+ *   - the column means and centred data (Def. of the centred variable,
+ *     Section 1.3),
+ *   - the d-th moment tensor m_i = (1/t) sum_l prod_k x_{l,i_k}
+ *     (Def. of the d-th moment, Section 1.3) in the block storage of
+ *     Section 2.1, only on sorted block tuples (Alg. 1 and Alg. 2, with the
+ *     sample range split into chunks and reduced as in Alg. 3),
+ *   - the cumulants c_2..c_dmax by the recursion of Section 3.2 (eq. cum_r;
+ *     Alg. 4 and Alg. 5): c_2 = m_2, c_3 = m_3, and for d >= 4 the central
+ *     moment minus the sum over partitions of the d positions into >= 2
+ *     parts of size >= 2 of products of lower-order cumulants.
+ * Normalisation is 1/t throughout (plug-in estimator, so c_2 is the biased
+ * covariance).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Data X is t x n, rows = samples, columns = variables (the data matrix of
+ *   Section 1.3), row-major with leading dimension ldx >= n.
+ * - Pointers are DEVICE pointers unless marked (host).  The caller owns every
+ *   buffer; the library never frees caller memory.  Scratch memory is the
+ *   caller's workspace, sized by cum_workspace_size().  The library keeps
+ *   small per-shape index tables of its own in device memory (allocated on
+ *   first use of a shape, freed at process exit).
+ * - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *   Work is enqueued asynchronously on it; outputs are valid once the stream
+ *   has reached that point.  Calls that share a workspace must not overlap.
+ * - Arguments are validated on the host before anything is enqueued; an
+ *   invalid call returns a status and enqueues nothing.  No C++ exception
+ *   crosses this boundary.  cum_last_error() gives a message for the last
+ *   failing call of the calling thread.
+ *
+ * Block storage (Section 2.1)
+ * ---------------------------
+ * With nbar = ceil(n/b), an order-d tensor is stored as the blocks of all
+ * sorted block tuples j_1 <= ... <= j_d over 0..nbar-1, in lexicographic
+ * order of the tuple; there are C(nbar+d-1, d) of them (the paper prints the
+ * binomial as C(nbar+d-1, nbar), which miscounts for nbar >= 3).  Each block
+ * is a padded b^d cube, in-block index row-major (first position slowest):
+ *   offset(j, r) = rank(j) * b^d + sum_k r_k * b^(d-1-k),
+ * holding the entry at variable multi-index (j_k*b + r_k)_k.  Diagonal blocks
+ * hold all b^d entries, redundant ones included (Alg. 1 loops over the whole
+ * block).  Positions whose variable index reaches n (ragged last block,
+ * b_l = n - b(nbar-1)) hold 0.
+ */
+#ifndef CUMULANTS_H
+#define CUMULANTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CUM_OK = 0,
+    CUM_EINVAL = -1,       /* invalid argument (nothing enqueued)              */
+    CUM_ENOMEM = -2,       /* workspace too small, or a table allocation failed */
+    CUM_EHIP = -3,         /* a HIP runtime call failed (see cum_last_error)   */
+    CUM_EUNSUPPORTED = -4  /* valid but unsupported combination                 */
+} cum_status;
+
+/* Arithmetic of the moment contraction (the sum over samples of Alg. 1).
+ * Centring, the cross-chunk reduction and the cumulant recursion are FP64 in
+ * every mode. */
+typedef enum {
+    CUM_F64 = 0,    /* FP64 data, FP64 matrix-core products and sums            */
+    CUM_F32 = 1,    /* FP32 data, FP32 matrix-core products, FP32 sums over at  */
+                    /* most 64 samples, then FP64                               */
+    CUM_BF16X2 = 2, /* FP32 data; each half-product split into two BF16 terms, */
+                    /* all 4 cross products on BF16 matrix cores, FP32 sums    */
+                    /* over at most 256 samples, then FP64                      */
+    CUM_BF16X3 = 3  /* as BF16X2 with a three-term split and the 6 cross       */
+                    /* products of combined weight >= 2^-16                     */
+} cum_prec;
+
+/* Block layout of one order (Section 2.1). */
+typedef struct {
+    int32_t n, d, b;
+    int32_t nbar;         /* ceil(n/b)                                       */
+    int32_t b_last;       /* n - b*(nbar-1), size of the ragged last block   */
+    int64_t nblocks;      /* C(nbar+d-1, d) sorted block tuples              */
+    int64_t block_elems;  /* b^d                                             */
+    int64_t elems;        /* nblocks * b^d stored doubles                    */
+} cum_layout;
+
+/* Largest supported order. */
+#define CUM_MAX_ORDER 8
+
+/* Host only.  Layout of the order-d block storage for n variables and block
+ * size b.  Requires n >= 1, 1 <= b <= n, 1 <= d <= CUM_MAX_ORDER. */
+cum_status cum_layout_query(int n, int d, int b, cum_layout *out /* host */);
+
+/* Host only.  Bytes of device workspace needed by cum_cumulants(t, n, d_max,
+ * b, prec); it is also enough for cum_center(t, n, prec) and for
+ * cum_moment_blocks(t, n, d, b, prec) with d <= d_max. */
+cum_status cum_workspace_size(int64_t t, int n, int d_max, int b, cum_prec prec, size_t *bytes /* host */);
+
+/* Column means and centred data (Def. of the centred variable, Section 1.3).
+ *   X     t x n FP64, leading dimension ldx >= n (read only)
+ *   mean  n FP64 out: mean[i] = (1/t) sum_l X[l][i] (compensated FP64 sums in a
+ *         fixed order)
+ *   Xc    t x n out, leading dimension n: X[l][i] - mean[i] computed in FP64,
+ *         stored as FP64 for CUM_F64 and rounded to FP32 (nearest-even) for
+ *         every other prec.  May be NULL (means only).
+ * Requires t >= 1, n >= 1. */
+cum_status cum_center(const double *X, int64_t t, int n, int64_t ldx, cum_prec prec, double *mean, void *Xc,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* Order-d moment tensor of the data AS GIVEN (no centring), in block storage
+ * (Def. of the d-th moment; Alg. 1 and 2; sample chunks reduced in FP64 in a
+ * fixed order as in Alg. 3, divided by t once).
+ *   Xc  t x n, leading dimension n, FP64 for CUM_F64, FP32 otherwise
+ *   M   cum_layout.elems FP64 out
+ * Requires t >= 1, 1 <= b <= n, 2 <= d <= CUM_MAX_ORDER.  Results are
+ * deterministic: the same call gives bitwise the same output. */
+cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, int d, int b, double *M, void *ws,
+                             size_t ws_bytes, void *stream);
+
+/* Cumulant tensors c_2..c_dmax of X (Alg. 5 for every order in turn).
+ *   X      t x n FP64, leading dimension ldx >= n
+ *   mean   n FP64 out (the first cumulant), or NULL
+ *   kappa  (host) array of d_max-1 device pointers; kappa[d-2] receives c_d
+ *          in block storage (cum_layout(n, d, b).elems FP64 each)
+ * The data are centred in FP64; only the moment contraction runs in prec.
+ * Requires t >= 1, 1 <= b <= n, 2 <= d_max <= CUM_MAX_ORDER. */
+cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
+                         double *mean, double *const *kappa /* host array */, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* Unfold an order-d block-stored tensor to the dense n^d array (first index
+ * slowest).  Entry i is read from the canonical stored copy: the position
+ * reached by sorting i_1..i_d ascending, so the output is exactly symmetric
+ * even where redundant stored copies differ in their last bits (Def. of a
+ * super-symmetric tensor, Section 1.3; block storage, Section 2.1). */
+cum_status cum_unfold(const double *blocks, int n, int d, int b, double *dense, void *stream);
+
+/* Host only.  Block-storage offset of the canonical stored copy of the
+ * multi-index idx[0..d-1] (each 0 <= idx[k] < n): the indices are sorted
+ * ascending first. */
+cum_status cum_stored_offset(int n, int d, int b, const int32_t *idx /* host */, int64_t *offset /* host */);
+
+/* ------------------------------------------------------------------------
+ * Batched cumulants: many datasets of the same width n and uneven sample
+ * counts, computed by one persistent launch of the moment contraction over
+ * all (dataset, tile, sample-chunk) work items, between one batched centring
+ * launch and one batched reduction/recursion launch per pair of orders, all
+ * captured once in a HIP graph and replayed.  Each dataset's result is
+ * bitwise the one cum_cumulants() gives for it with the same prec.
+ * ------------------------------------------------------------------------ */
+typedef struct cum_batch cum_batch;
+
+/* Host only (allocates the plan's device memory).  t_i (host, n_sets
+ * entries, each >= 1). */
+cum_status cum_batch_create(int n_sets, const int64_t *t_i /* host */, int n, int d_max, int b, cum_prec prec,
+                            cum_batch **plan /* host out */);
+
+/*   X_i    (host) n_sets device pointers, dataset s is t_i[s] x n FP64, ld n
+ *   kappa  (host) n_sets*(d_max-1) device pointers: kappa[s*(d_max-1)+d-2]
+ *          receives c_d of dataset s in block storage
+ *   mean   (host) n_sets device pointers (n FP64 each) or NULL
+ * The first call captures the graph on stream; later calls copy the pointer
+ * tables and replay it. */
+cum_status cum_batch_run(cum_batch *plan, const double *const *X_i, double *const *kappa, double *const *mean,
+                         void *stream);
+
+/* Host only.  After a cum_batch_run has completed: per-dataset device
+ * timestamps (ticks of the 100 MHz constant clock), written when the
+ * dataset's last order was finalised, and the start timestamp of the run.
+ * ticks: n_sets entries.  Frequency in Hz goes to *hz. */
+cum_status cum_batch_timestamps(cum_batch *plan, uint64_t *start /* host */, uint64_t *ticks /* host */,
+                                double *hz /* host */);
+
+cum_status cum_batch_destroy(cum_batch *plan);
+
+/* Host only.  Check that the moment-contraction tiling of order d covers
+ * every stored entry exactly once (no GPU needed).  Returns CUM_OK or
+ * CUM_EINVAL with a message. */
+cum_status cum_plan_check(int n, int d, int b);
+
+/* Host only.  Measurement helpers.  While enabled on the calling thread,
+ * every kernel launch made by the entry points on that thread is bracketed by
+ * two HIP events recorded on the launch's own stream.  cum_timing_read waits
+ * for those events, writes the summed milliseconds and the launch count per
+ * kernel kind (CUM_KIND_* below; arrays of CUM_NKINDS entries, host) and
+ * forgets them.  Disabled by default; enabling adds two event records per
+ * launch. */
+#define CUM_KIND_CENTER 0  /* column sums, means, centring                   */
+#define CUM_KIND_MOMENT 1  /* block moment contraction                       */
+#define CUM_KIND_REDUCE 2  /* chunk reduction + cumulant recursion           */
+#define CUM_KIND_UNFOLD 3  /* unfold to dense                                */
+#define CUM_KIND_BATCH 4   /* a whole batched run (graph launch)             */
+#define CUM_NKINDS 5
+cum_status cum_timing_enable(int on);
+cum_status cum_timing_read(double *ms /* host */, int64_t *launches /* host */);
+
+const char *cum_status_str(cum_status s);
+const char *cum_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUMULANTS_H */

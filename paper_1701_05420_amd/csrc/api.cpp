@@ -1,0 +1,818 @@
+// Host planner and C ABI (include/cumulants.h).
+//
+// For each (n, b, d) the planner builds, once, the row (prefix) and column
+// (suffix) feature tables of the order's contraction, the (v, w) rank table,
+// per-32-block validity bounds, the sorted block tuples and the partition
+// masks used by the recursion, and uploads them.  For each call shape it
+// builds the tile list and the work-item list (tiles x sample chunks, ordered
+// so that all items of one chunk land on the same XCD).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cumulants.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace cum {
+
+static thread_local std::string g_last_error;
+
+static cum_status fail(cum_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                             \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(CUM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// optional per-launch timing with HIP events on the launch's stream
+// ---------------------------------------------------------------------------
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int kind;
+};
+static thread_local bool g_timing = false;
+static thread_local std::vector<TimedLaunch> g_timed;
+
+template <typename F>
+static hipError_t timed(int kind, hipStream_t s, F &&launch) {
+    if (!g_timing) return launch();
+    TimedLaunch tl{nullptr, nullptr, kind};
+    hipError_t e;
+    if ((e = hipEventCreate(&tl.a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&tl.b)) != hipSuccess) return e;
+    if ((e = hipEventRecord(tl.a, s)) != hipSuccess) return e;
+    e = launch();
+    hipError_t e2 = hipEventRecord(tl.b, s);
+    g_timed.push_back(tl);
+    return e != hipSuccess ? e : e2;
+}
+
+// ---------------------------------------------------------------------------
+// combinatorics (host)
+// ---------------------------------------------------------------------------
+static int64_t binom(int64_t a, int64_t r) {
+    if (r < 0 || a < r) return 0;
+    __int128 v = 1;
+    for (int64_t i = 1; i <= r; ++i) {
+        v = v * (a - r + i) / i;
+        if (v > (__int128)INT64_MAX) return -1;
+    }
+    return (int64_t)v;
+}
+
+static int64_t ipow64(int64_t b, int e) {
+    int64_t r = 1;
+    for (int k = 0; k < e; ++k) r *= b;
+    return r;
+}
+
+// Term of the lexicographic rank contributed by tuple position k of an
+// order-d tuple, moving from previous entry a to entry c.
+static int64_t rank_term(int nbar, int d, int k, int a, int c) {
+    return binom(nbar - a + d - k - 1, d - k) - binom(nbar - c + d - k - 1, d - k);
+}
+
+static int64_t rank_sorted_host(const int *u, int m, int nbar) {
+    int64_t s = 0;
+    int prev = 0;
+    for (int k = 0; k < m; ++k) {
+        s += rank_term(nbar, m, k, prev, u[k]);
+        prev = u[k];
+    }
+    return s;
+}
+
+// All sorted (non-decreasing) m-tuples over 0..nbar-1 in lexicographic order.
+static std::vector<std::vector<int>> sorted_tuples(int nbar, int m) {
+    std::vector<std::vector<int>> out;
+    std::vector<int> u(m, 0);
+    if (m == 0) {
+        out.push_back(u);
+        return out;
+    }
+    while (true) {
+        out.push_back(u);
+        int k = m - 1;
+        while (k >= 0 && u[k] == nbar - 1) --k;
+        if (k < 0) break;
+        int v = u[k] + 1;
+        for (int q = k; q < m; ++q) u[q] = v;
+    }
+    return out;
+}
+
+// Set partitions of d positions with every part of size >= 2 and at least
+// two parts, as position masks.  Restricted growth strings a_0..a_{d-1}
+// (a_0 = 0, a_k <= 1 + max of the earlier entries) are visited in
+// lexicographic order, advancing the rightmost entry that can still grow
+// (Knuth's Algorithm 7.2.1.5H, the generator the paper cites), and filtered.
+static std::vector<std::vector<uint16_t>> recursion_partitions(int d) {
+    std::vector<std::vector<uint16_t>> out;
+    if (d < 4) return out;
+    std::vector<int> a(d, 0);
+    while (true) {
+        int nparts = 0;
+        for (int k = 0; k < d; ++k) nparts = std::max(nparts, a[k] + 1);
+        std::vector<uint16_t> masks(nparts, 0);
+        for (int k = 0; k < d; ++k) masks[a[k]] |= (uint16_t)(1u << k);
+        bool ok = nparts >= 2;
+        for (uint16_t m : masks)
+            if (__builtin_popcount(m) < 2) ok = false;
+        if (ok) out.push_back(masks);
+        int k = d - 1;
+        while (k >= 1) {
+            int lim = 0;
+            for (int q = 0; q < k; ++q) lim = std::max(lim, a[q] + 1);
+            if (a[k] < lim) break;
+            --k;
+        }
+        if (k < 1) break;
+        ++a[k];
+        for (int q = k + 1; q < d; ++q) a[q] = 0;
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// device buffers owned by the library
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+template <typename T>
+static cum_status upload(DevBuf &dst, const std::vector<T> &src) {
+    size_t bytes = std::max<size_t>(sizeof(T), src.size() * sizeof(T));
+    if (dst.p) {
+        (void)hipFree(dst.p);
+        dst.p = nullptr;
+    }
+    HIP_TRY(hipMalloc(&dst.p, bytes));
+    if (!src.empty()) HIP_TRY(hipMemcpy(dst.p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CUM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-order plan
+// ---------------------------------------------------------------------------
+struct OrderPlan {
+    int n = 0, b = 0, d = 0, p = 0, q = 0, nbar = 0, nr = 0, nc = 0;
+    int64_t nblocks = 0, elems = 0;
+    std::vector<Feat> rows, cols;
+    std::vector<int32_t> rb_vmin, cb_wmax;
+    std::vector<int64_t> H;
+    std::vector<uint8_t> tuples;
+    std::vector<uint16_t> parts;  // npart x MAXPARTS
+    int npart = 0;
+    bool uploaded = false;
+    DevBuf rows_d, cols_d, rbv_d, cbw_d, H_d, tuples_d, parts_d;
+};
+
+static cum_status build_order(int n, int b, int d, OrderPlan &o) {
+    o.n = n;
+    o.b = b;
+    o.d = d;
+    o.p = d / 2;
+    o.q = d - o.p;
+    o.nbar = (n + b - 1) / b;
+    const int nbar = o.nbar, p = o.p, q = o.q;
+    const int64_t bd = ipow64(b, d), bq = ipow64(b, q);
+    o.nblocks = binom(nbar + d - 1, d);
+    if (o.nblocks < 0) return fail(CUM_EINVAL, "order %d with %d blocks per mode overflows", d, nbar);
+    o.elems = o.nblocks * bd;
+
+    // rows: sorted prefixes ordered by their last block (then lexicographically)
+    auto P = sorted_tuples(nbar, p);
+    std::stable_sort(P.begin(), P.end(), [](const std::vector<int> &x, const std::vector<int> &y) {
+        return x.back() < y.back();
+    });
+    const int64_t bp = ipow64(b, p);
+    for (const auto &u : P) {
+        int64_t part = 0;
+        int prev = 0;
+        for (int k = 0; k < p; ++k) {
+            part += rank_term(nbar, d, k, prev, u[k]);
+            prev = u[k];
+        }
+        for (int64_t ip = 0; ip < bp; ++ip) {
+            Feat f;
+            f.addr = part * bd + ip * bq;
+            f.blk = u[p - 1];
+            int64_t x = ip;
+            int dig[MAXH] = {0};
+            for (int k = p - 1; k >= 0; --k) {
+                dig[k] = (int)(x % b);
+                x /= b;
+            }
+            for (int k = 0; k < MAXH; ++k) {
+                int v = k < p ? u[k] * b + dig[k] : n;
+                f.var[k] = (uint8_t)(v < n ? v : n);
+            }
+            o.rows.push_back(f);
+        }
+    }
+    // columns: sorted suffixes in lexicographic order (so by their first block)
+    auto Q = sorted_tuples(nbar, q);
+    for (const auto &u : Q) {
+        int64_t part = 0;
+        int prev = u[0];
+        for (int k = p + 1; k < d; ++k) {
+            part += rank_term(nbar, d, k, prev, u[k - p]);
+            prev = u[k - p];
+        }
+        for (int64_t iq = 0; iq < bq; ++iq) {
+            Feat f;
+            f.addr = part * bd + iq;
+            f.blk = u[0];
+            int64_t x = iq;
+            int dig[MAXH] = {0};
+            for (int k = q - 1; k >= 0; --k) {
+                dig[k] = (int)(x % b);
+                x /= b;
+            }
+            for (int k = 0; k < MAXH; ++k) {
+                int v = k < q ? u[k] * b + dig[k] : n;
+                f.var[k] = (uint8_t)(v < n ? v : n);
+            }
+            o.cols.push_back(f);
+        }
+    }
+    const int nr_real = (int)o.rows.size(), nc_real = (int)o.cols.size();
+    o.nr = (nr_real + FEAT_BLOCK - 1) / FEAT_BLOCK * FEAT_BLOCK;
+    o.nc = (nc_real + FEAT_BLOCK - 1) / FEAT_BLOCK * FEAT_BLOCK;
+    Feat padr{0, INT32_MAX, {(uint8_t)n, (uint8_t)n, (uint8_t)n, (uint8_t)n}};
+    Feat padc{0, -1, {(uint8_t)n, (uint8_t)n, (uint8_t)n, (uint8_t)n}};
+    o.rows.resize(o.nr, padr);
+    o.cols.resize(o.nc, padc);
+    for (int rb = 0; rb < o.nr / FEAT_BLOCK; ++rb) {
+        int32_t v = INT32_MAX;
+        for (int r = rb * FEAT_BLOCK; r < std::min(nr_real, (rb + 1) * FEAT_BLOCK); ++r) v = std::min(v, o.rows[r].blk);
+        o.rb_vmin.push_back(v);
+    }
+    for (int cb = 0; cb < o.nc / FEAT_BLOCK; ++cb) {
+        int32_t w = -1;
+        for (int c = cb * FEAT_BLOCK; c < std::min(nc_real, (cb + 1) * FEAT_BLOCK); ++c) w = std::max(w, o.cols[c].blk);
+        o.cb_wmax.push_back(w);
+    }
+    o.H.assign((size_t)nbar * nbar, 0);
+    for (int v = 0; v < nbar; ++v)
+        for (int w = v; w < nbar; ++w) o.H[(size_t)v * nbar + w] = bd * rank_term(nbar, d, p, v, w);
+
+    // recursion tables
+    auto T = sorted_tuples(nbar, d);
+    for (const auto &u : T)
+        for (int k = 0; k < d; ++k) o.tuples.push_back((uint8_t)u[k]);
+    auto parts = recursion_partitions(d);
+    o.npart = (int)parts.size();
+    for (const auto &pm : parts)
+        for (int k = 0; k < MAXPARTS; ++k) o.parts.push_back(k < (int)pm.size() ? pm[k] : 0);
+
+    return CUM_OK;
+}
+
+static cum_status upload_order(OrderPlan &o) {
+    if (o.uploaded) return CUM_OK;
+    cum_status st;
+    if ((st = upload(o.rows_d, o.rows)) || (st = upload(o.cols_d, o.cols)) || (st = upload(o.rbv_d, o.rb_vmin)) ||
+        (st = upload(o.cbw_d, o.cb_wmax)) || (st = upload(o.H_d, o.H)) || (st = upload(o.tuples_d, o.tuples)) ||
+        (st = upload(o.parts_d, o.parts)))
+        return st;
+    o.uploaded = true;
+    return CUM_OK;
+}
+
+static std::mutex g_mu;
+static std::map<std::tuple<int, int, int>, std::unique_ptr<OrderPlan>> g_orders;
+
+static cum_status get_order(int n, int b, int d, OrderPlan **out) {
+    auto key = std::make_tuple(n, b, d);
+    auto it = g_orders.find(key);
+    if (it != g_orders.end()) {
+        *out = it->second.get();
+        return CUM_OK;
+    }
+    std::unique_ptr<OrderPlan> o(new OrderPlan);
+    cum_status st = build_order(n, b, d, *o);
+    if (st) return st;
+    *out = o.get();
+    g_orders[key] = std::move(o);
+    return CUM_OK;
+}
+
+// Work-group tiles of one order: WM x WN 32-blocks per wave, 2 x 2 waves.
+// Only tiles holding a stored entry are kept; cost = stored 32-blocks.
+struct HostTile {
+    TileDev t;
+    int cost;
+};
+
+static void order_tiles(const OrderPlan &o, int wm, int wn, int ord_index, std::vector<HostTile> &out) {
+    const int TM = 2 * wm * 32, TN = 2 * wn * 32;
+    for (int r0 = 0; r0 < o.nr; r0 += TM)
+        for (int c0 = 0; c0 < o.nc; c0 += TN) {
+            int cost = 0;
+            for (int rb = r0 / 32; rb < std::min(o.nr, r0 + TM) / 32; ++rb)
+                for (int cb = c0 / 32; cb < std::min(o.nc, c0 + TN) / 32; ++cb)
+                    if (o.rb_vmin[rb] <= o.cb_wmax[cb]) ++cost;
+            if (cost) out.push_back({{ord_index, r0, c0, 0}, cost});
+        }
+}
+
+static void shape_dims(int shape, int &wm, int &wn) {
+    wm = shape == TS_2x1 ? 2 : 1;
+    wn = 1;
+}
+
+// ---------------------------------------------------------------------------
+// call plan: all orders dlo..dhi of one (n, b), one precision and tile shape,
+// one sample count.
+// ---------------------------------------------------------------------------
+struct CallPlan {
+    int n = 0, b = 0, dlo = 0, dhi = 0, prec = 0, shape = 0, kt = 0;
+    int64_t t = 0, chunk_len = 0, nchunks = 0, stride = 0, nitems = 0;
+    std::vector<OrderPlan *> orders;  // index d - dlo
+    std::vector<int64_t> out_off;     // index d - dlo
+    std::vector<OrderDev> ods;
+    std::vector<TileDev> tdev;
+    std::vector<Item> items;
+    std::vector<RedOrder> red;        // index d - dlo
+    bool uploaded = false;
+    DevBuf ords_d, tiles_d, items_d, red_d;
+};
+
+// Upload the call's order tables (filling in their device pointers) and its
+// tile, item and reduction records.
+static cum_status upload_call(CallPlan &c) {
+    if (c.uploaded) return CUM_OK;
+    cum_status st;
+    for (size_t i = 0; i < c.orders.size(); ++i) {
+        OrderPlan *o = c.orders[i];
+        if ((st = upload_order(*o))) return st;
+        c.ods[i].rows = (const Feat *)o->rows_d.p;
+        c.ods[i].cols = (const Feat *)o->cols_d.p;
+        c.ods[i].rb_vmin = (const int32_t *)o->rbv_d.p;
+        c.ods[i].cb_wmax = (const int32_t *)o->cbw_d.p;
+        c.ods[i].H = (const int64_t *)o->H_d.p;
+        c.red[i].tuples = (const uint8_t *)o->tuples_d.p;
+        c.red[i].parts = (const uint16_t *)o->parts_d.p;
+    }
+    if ((st = upload(c.ords_d, c.ods)) || (st = upload(c.tiles_d, c.tdev)) || (st = upload(c.items_d, c.items)) ||
+        (st = upload(c.red_d, c.red)))
+        return st;
+    c.uploaded = true;
+    return CUM_OK;
+}
+
+static std::map<std::tuple<int, int, int, int, int, int, int64_t>, std::unique_ptr<CallPlan>> g_calls;
+
+static int choose_kt(int prec, int n) {
+    int kt = (16 * 256 / n) / 16 * 16;
+    int ktmax = prec == P_F64 ? 32 : (prec == P_F32 ? 64 : 128);
+    return std::max(16, std::min(kt, ktmax));
+}
+
+static int default_shape(int prec) { return prec == P_F64 ? TS_1x1 : TS_2x1; }
+
+static cum_status get_call(int n, int b, int dlo, int dhi, int prec, int shape, int64_t t, CallPlan **out) {
+    auto key = std::make_tuple(n, b, dlo, dhi, prec, shape, t);
+    auto it = g_calls.find(key);
+    if (it != g_calls.end()) {
+        *out = it->second.get();
+        return CUM_OK;
+    }
+    std::unique_ptr<CallPlan> c(new CallPlan);
+    c->n = n;
+    c->b = b;
+    c->dlo = dlo;
+    c->dhi = dhi;
+    c->prec = prec;
+    c->shape = shape;
+    c->t = t;
+    c->kt = choose_kt(prec, n);
+    int wm, wn;
+    shape_dims(shape, wm, wn);
+    std::vector<HostTile> tiles;
+    int64_t off = 0;
+    for (int d = dlo; d <= dhi; ++d) {
+        OrderPlan *o;
+        cum_status st = get_order(n, b, d, &o);
+        if (st) return st;
+        c->orders.push_back(o);
+        c->out_off.push_back(off);
+        OrderDev od;
+        od.rows = nullptr;
+        od.cols = nullptr;
+        od.rb_vmin = nullptr;
+        od.cb_wmax = nullptr;
+        od.H = nullptr;
+        od.out_off = off;
+        od.elems = o->elems;
+        od.d = d;
+        od.p = o->p;
+        od.q = o->q;
+        od.nbar = o->nbar;
+        od.b = b;
+        od.nr = o->nr;
+        od.nc = o->nc;
+        od.pad = 0;
+        c->ods.push_back(od);
+        order_tiles(*o, wm, wn, d - dlo, tiles);
+        RedOrder ro;
+        ro.tuples = nullptr;
+        ro.parts = nullptr;
+        ro.nblocks = o->nblocks;
+        ro.out_off = off;
+        ro.d = d;
+        ro.npart = o->npart;
+        ro.nbar = o->nbar;
+        ro.b = b;
+        c->red.push_back(ro);
+        off += o->elems;
+    }
+    c->stride = off;
+    // expensive tiles first, so that the tail of each XCD's queue is short
+    std::stable_sort(tiles.begin(), tiles.end(), [](const HostTile &x, const HostTile &y) { return x.cost > y.cost; });
+    const int64_t ntiles = (int64_t)tiles.size();
+    // sample chunks: enough items to fill 256 CUs twice over, chunks of >= 256 samples
+    int64_t want = (1024 + ntiles - 1) / ntiles;
+    int64_t maxch = std::max<int64_t>(1, t / 256);
+    int64_t nch = std::max<int64_t>(1, std::min(want, maxch));
+    if (nch >= 8) nch = (nch + 7) / 8 * 8;
+    c->chunk_len = (t + nch - 1) / nch;
+    c->nchunks = (t + c->chunk_len - 1) / c->chunk_len;
+    // items: chunk ch is processed on XCD (ch % 8); WG i runs on XCD (i % 8)
+    std::vector<std::vector<Item>> per_xcd(8);
+    for (int64_t ch = 0; ch < c->nchunks; ++ch)
+        for (int64_t ti = 0; ti < ntiles; ++ti) per_xcd[ch % 8].push_back({(int32_t)ti, (int32_t)ch, 0, 0});
+    size_t longest = 0;
+    for (auto &v : per_xcd) longest = std::max(longest, v.size());
+    std::vector<Item> items;
+    for (size_t s = 0; s < longest; ++s)
+        for (int x = 0; x < 8; ++x) items.push_back(s < per_xcd[x].size() ? per_xcd[x][s] : Item{-1, 0, 0, 0});
+    while (!items.empty() && items.back().tile < 0) items.pop_back();
+    c->nitems = (int64_t)items.size();
+    c->items = std::move(items);
+    for (auto &h : tiles) c->tdev.push_back(h.t);
+    *out = c.get();
+    g_calls[key] = std::move(c);
+    return CUM_OK;
+}
+
+static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+static void center_groups(int64_t t, int &groups, int64_t &rows_per) {
+    int64_t g = std::min<int64_t>(1024, (t + 255) / 256);
+    if (g < 1) g = 1;
+    rows_per = (t + g - 1) / g;
+    groups = (int)((t + rows_per - 1) / rows_per);
+}
+
+static int esize(int prec) { return prec == P_F64 ? 8 : 4; }
+
+static cum_status check_common(int64_t t, int n, int b) {
+    if (t < 1) return fail(CUM_EINVAL, "t must be >= 1 (got %lld)", (long long)t);
+    if (n < 1 || n > MAXN) return fail(CUM_EINVAL, "n must be in 1..%d (got %d)", MAXN, n);
+    if (b < 1 || b > n) return fail(CUM_EINVAL, "b must be in 1..n (got b=%d, n=%d)", b, n);
+    return CUM_OK;
+}
+
+static cum_status check_prec(int prec) {
+    if (prec < CUM_F64 || prec > CUM_BF16X3) return fail(CUM_EUNSUPPORTED, "unknown precision %d", prec);
+    return CUM_OK;
+}
+
+// moment contraction + reduction for orders dlo..dhi into kappa (and the
+// recursion for d >= 4 when recursion is set)
+static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, double *const *outs, bool recursion,
+                             hipStream_t s) {
+    cum_status st = upload_call(*c);
+    if (st) return st;
+    MomentArgs ma;
+    ma.ords = (const OrderDev *)c->ords_d.p;
+    ma.tiles = (const TileDev *)c->tiles_d.p;
+    ma.items = (const Item *)c->items_d.p;
+    ma.nitems = c->nitems;
+    ma.sets = nullptr;
+    ma.set0.X = Xc;
+    ma.set0.t = c->t;
+    ma.set0.chunk_len = c->chunk_len;
+    ma.set0.nchunks = c->nchunks;
+    ma.set0.partial = partial;
+    ma.set0.stride = c->stride;
+    ma.n = c->n;
+    ma.kt = c->kt;
+    if (c->nitems > 0)
+        HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, ma, (int)c->nitems, s); }));
+    // reduction (+ recursion) in pairs of orders {d, d+1}: order d needs
+    // cumulants up to d-2 only, so a pair depends only on earlier pairs
+    const RedOrder *red_d = (const RedOrder *)c->red_d.p;
+    for (int d = c->dlo; d <= c->dhi; d += 2) {
+        RedArgs ra;
+        const int i0 = d - c->dlo;
+        ra.ords = red_d + i0;
+        ra.nords = (d + 1 <= c->dhi) ? 2 : 1;
+        ra.recursion = recursion ? 1 : 0;
+        ra.nb0 = c->red[i0].nblocks;
+        ra.nbtot = ra.nb0 + (ra.nords == 2 ? c->red[i0 + 1].nblocks : 0);
+        ra.sets = nullptr;
+        ra.set0.partial = partial;
+        ra.set0.stride = c->stride;
+        ra.set0.nchunks = c->nchunks;
+        ra.set0.t = c->t;
+        for (int k = 0; k < MAXD - 1; ++k) ra.set0.kappa[k] = nullptr;
+        for (int dd = c->dlo; dd <= c->dhi; ++dd) ra.set0.kappa[dd - 2] = outs[dd - c->dlo];
+        ra.set0.stamp = nullptr;
+        if (!recursion) {
+            // plain moments: no order reads another, one launch for all
+            ra.nords = 1;
+            ra.nbtot = ra.nb0;
+        }
+        HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(ra, 1, s); }));
+        if (!recursion) {
+            for (int dd = d + 1; dd <= c->dhi; ++dd) {
+                RedArgs rb = ra;
+                rb.ords = red_d + (dd - c->dlo);
+                rb.nb0 = rb.nbtot = c->red[dd - c->dlo].nblocks;
+                HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(rb, 1, s); }));
+            }
+            break;
+        }
+    }
+    return CUM_OK;
+}
+
+}  // namespace cum
+
+using namespace cum;
+
+extern "C" {
+
+const char *cum_status_str(cum_status s) {
+    switch (s) {
+        case CUM_OK: return "CUM_OK";
+        case CUM_EINVAL: return "CUM_EINVAL: invalid argument";
+        case CUM_ENOMEM: return "CUM_ENOMEM: workspace too small or allocation failed";
+        case CUM_EHIP: return "CUM_EHIP: HIP runtime error";
+        case CUM_EUNSUPPORTED: return "CUM_EUNSUPPORTED: unsupported combination";
+    }
+    return "unknown status";
+}
+
+const char *cum_last_error(void) { return g_last_error.c_str(); }
+
+cum_status cum_layout_query(int n, int d, int b, cum_layout *out) {
+    if (!out) return fail(CUM_EINVAL, "out is NULL");
+    if (n < 1 || b < 1 || b > n) return fail(CUM_EINVAL, "need n >= 1 and 1 <= b <= n (n=%d, b=%d)", n, b);
+    if (d < 1 || d > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d must be in 1..%d (got %d)", CUM_MAX_ORDER, d);
+    const int nbar = (n + b - 1) / b;
+    const int64_t nb = binom(nbar + d - 1, d);
+    if (nb < 0) return fail(CUM_EINVAL, "layout size overflows");
+    out->n = n;
+    out->d = d;
+    out->b = b;
+    out->nbar = nbar;
+    out->b_last = n - b * (nbar - 1);
+    out->nblocks = nb;
+    out->block_elems = ipow64(b, d);
+    out->elems = nb * out->block_elems;
+    return CUM_OK;
+}
+
+cum_status cum_stored_offset(int n, int d, int b, const int32_t *idx, int64_t *offset) {
+    cum_layout L;
+    cum_status st = cum_layout_query(n, d, b, &L);
+    if (st) return st;
+    if (!idx || !offset) return fail(CUM_EINVAL, "NULL argument");
+    int v[CUM_MAX_ORDER], j[CUM_MAX_ORDER];
+    for (int k = 0; k < d; ++k) {
+        if (idx[k] < 0 || idx[k] >= n) return fail(CUM_EINVAL, "index %d out of range", idx[k]);
+        v[k] = idx[k];
+    }
+    std::sort(v, v + d);
+    int64_t in = 0;
+    for (int k = 0; k < d; ++k) {
+        j[k] = v[k] / b;
+        in = in * b + (v[k] - j[k] * b);
+    }
+    *offset = rank_sorted_host(j, d, L.nbar) * L.block_elems + in;
+    return CUM_OK;
+}
+
+cum_status cum_workspace_size(int64_t t, int n, int d_max, int b, cum_prec prec, size_t *bytes) {
+    if (!bytes) return fail(CUM_EINVAL, "bytes is NULL");
+    cum_status st;
+    if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;
+    if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
+    std::lock_guard<std::mutex> lk(g_mu);
+    int groups;
+    int64_t rows_per;
+    center_groups(t, groups, rows_per);
+    size_t total = align_up((size_t)t * n * esize(prec)) + align_up((size_t)groups * n * 2 * 8) + align_up((size_t)n * 8);
+    CallPlan *c;
+    if ((st = get_call(n, b, 2, d_max, prec, default_shape(prec), t, &c))) return st;
+    size_t part = (size_t)c->nchunks * c->stride * 8;
+    // a single-order moment call uses its own plan; cover the largest one
+    for (int d = 2; d <= d_max; ++d) {
+        CallPlan *c1;
+        if ((st = get_call(n, b, d, d, prec, default_shape(prec), t, &c1))) return st;
+        part = std::max(part, (size_t)c1->nchunks * c1->stride * 8);
+    }
+    *bytes = total + align_up(part);
+    return CUM_OK;
+}
+
+static cum_status center_impl(const double *X, int64_t t, int n, int64_t ldx, int prec, double *mean, void *Xc,
+                              char *ws, size_t ws_bytes, hipStream_t s) {
+    int groups;
+    int64_t rows_per;
+    center_groups(t, groups, rows_per);
+    size_t need = align_up((size_t)groups * n * 2 * 8);
+    if (ws_bytes < need || !ws) return fail(CUM_ENOMEM, "centring needs %zu workspace bytes", need);
+    double *part = (double *)ws;
+    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_colsum(X, t, n, ldx, rows_per, groups, part, s); }));
+    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_mean(part, groups, n, t, mean, s); }));
+    if (Xc) HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_center(X, t, n, ldx, mean, Xc, prec, s); }));
+    return CUM_OK;
+}
+
+cum_status cum_center(const double *X, int64_t t, int n, int64_t ldx, cum_prec prec, double *mean, void *Xc,
+                      void *ws, size_t ws_bytes, void *stream) {
+    cum_status st;
+    if ((st = check_common(t, n, 1)) || (st = check_prec(prec))) return st;
+    if (!X || !mean) return fail(CUM_EINVAL, "X and mean must not be NULL");
+    if (ldx < n) return fail(CUM_EINVAL, "ldx (%lld) < n (%d)", (long long)ldx, n);
+    return center_impl(X, t, n, ldx, prec, mean, Xc, (char *)ws, ws_bytes, (hipStream_t)stream);
+}
+
+cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, int d, int b, double *M, void *ws,
+                             size_t ws_bytes, void *stream) {
+    cum_status st;
+    if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;
+    if (d < 2 || d > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d must be in 2..%d", CUM_MAX_ORDER);
+    if (!Xc || !M) return fail(CUM_EINVAL, "Xc and M must not be NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    CallPlan *c;
+    if ((st = get_call(n, b, d, d, prec, default_shape(prec), t, &c))) return st;
+    size_t need = align_up((size_t)c->nchunks * c->stride * 8);
+    if (!ws || ws_bytes < need) return fail(CUM_ENOMEM, "moment_blocks needs %zu workspace bytes", need);
+    double *outs[1] = {M};
+    return run_orders(c, Xc, (double *)ws, outs, false, (hipStream_t)stream);
+}
+
+cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
+                         double *mean, double *const *kappa, void *ws, size_t ws_bytes, void *stream) {
+    cum_status st;
+    if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;
+    if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
+    if (!X || !kappa) return fail(CUM_EINVAL, "X and kappa must not be NULL");
+    if (ldx < n) return fail(CUM_EINVAL, "ldx (%lld) < n (%d)", (long long)ldx, n);
+    for (int d = 2; d <= d_max; ++d)
+        if (!kappa[d - 2]) return fail(CUM_EINVAL, "kappa[%d] is NULL", d - 2);
+    std::lock_guard<std::mutex> lk(g_mu);
+    CallPlan *c;
+    if ((st = get_call(n, b, 2, d_max, prec, default_shape(prec), t, &c))) return st;
+    int groups;
+    int64_t rows_per;
+    center_groups(t, groups, rows_per);
+    const size_t xbytes = align_up((size_t)t * n * esize(prec));
+    const size_t cbytes = align_up((size_t)groups * n * 2 * 8);
+    const size_t mbytes = align_up((size_t)n * 8);
+    const size_t pbytes = align_up((size_t)c->nchunks * c->stride * 8);
+    const size_t need = xbytes + cbytes + mbytes + pbytes;
+    if (!ws || ws_bytes < need) return fail(CUM_ENOMEM, "cumulants needs %zu workspace bytes (got %zu)", need, ws_bytes);
+    char *w = (char *)ws;
+    void *Xc = w;
+    char *cw = w + xbytes;
+    double *mtmp = (double *)(w + xbytes + cbytes);
+    double *partial = (double *)(w + xbytes + cbytes + mbytes);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = center_impl(X, t, n, ldx, prec, mean ? mean : mtmp, Xc, cw, cbytes, s))) return st;
+    return run_orders(c, Xc, partial, kappa, true, s);
+}
+
+cum_status cum_unfold(const double *blocks, int n, int d, int b, double *dense, void *stream) {
+    cum_layout L;
+    cum_status st = cum_layout_query(n, d, b, &L);
+    if (st) return st;
+    if (!blocks || !dense) return fail(CUM_EINVAL, "NULL buffer");
+    HIP_TRY(timed(CUM_KIND_UNFOLD, (hipStream_t)stream,
+                  [&] { return launch_unfold(blocks, n, d, b, dense, (hipStream_t)stream); }));
+    return CUM_OK;
+}
+
+cum_status cum_plan_check(int n, int d, int b) {
+    cum_status st;
+    if ((st = check_common(1, n, b))) return st;
+    if (d < 2 || d > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d must be in 2..%d", CUM_MAX_ORDER);
+    OrderPlan o;
+    if ((st = build_order(n, b, d, o))) return st;  // host tables only, nothing uploaded
+    const int64_t be = ipow64(b, d);
+    auto T = sorted_tuples(o.nbar, d);
+    for (int shape : {TS_1x1, TS_2x1}) {
+        int wm, wn;
+        shape_dims(shape, wm, wn);
+        std::vector<HostTile> tiles;
+        order_tiles(o, wm, wn, 0, tiles);
+        std::vector<uint8_t> hits((size_t)o.elems, 0);
+        const int TM = 2 * wm * 32, TN = 2 * wn * 32;
+        for (const auto &ht : tiles) {
+            for (int r = ht.t.row0; r < std::min(o.nr, ht.t.row0 + TM); ++r)
+                for (int c = ht.t.col0; c < std::min(o.nc, ht.t.col0 + TN); ++c) {
+                    const Feat &fr = o.rows[r], &fc = o.cols[c];
+                    const bool stored = fr.blk <= fc.blk;
+                    const bool computed = o.rb_vmin[r / 32] <= o.cb_wmax[c / 32];
+                    if (stored && !computed)
+                        return fail(CUM_EINVAL, "d=%d: entry (%d,%d) lies in a skipped block", d, r, c);
+                    if (!stored) continue;
+                    const int64_t addr = fr.addr + fc.addr + o.H[(size_t)fr.blk * o.nbar + fc.blk];
+                    if (addr < 0 || addr >= o.elems) return fail(CUM_EINVAL, "d=%d: address %lld out of range", d, (long long)addr);
+                    if (hits[(size_t)addr]++) return fail(CUM_EINVAL, "d=%d: address %lld written twice", d, (long long)addr);
+                    // the variables multiplied there must be the ones stored there
+                    const auto &j = T[(size_t)(addr / be)];
+                    int64_t in = addr % be;
+                    int dig[CUM_MAX_ORDER];
+                    for (int k = d - 1; k >= 0; --k) {
+                        dig[k] = (int)(in % b);
+                        in /= b;
+                    }
+                    for (int k = 0; k < d; ++k) {
+                        int v = j[k] * b + dig[k];
+                        if (v > n) v = n;
+                        const int have = k < o.p ? fr.var[k] : fc.var[k - o.p];
+                        if (have != v)
+                            return fail(CUM_EINVAL, "d=%d: variable mismatch at address %lld", d, (long long)addr);
+                    }
+                }
+        }
+        for (size_t e = 0; e < hits.size(); ++e)
+            if (hits[e] != 1) return fail(CUM_EINVAL, "d=%d: address %zu never written", d, e);
+    }
+    return CUM_OK;
+}
+
+cum_status cum_timing_enable(int on) {
+    g_timing = on != 0;
+    return CUM_OK;
+}
+
+cum_status cum_timing_read(double *ms, int64_t *launches) {
+    if (!ms || !launches) return fail(CUM_EINVAL, "NULL argument");
+    for (int k = 0; k < CUM_NKINDS; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    cum_status st = CUM_OK;
+    for (auto &tl : g_timed) {
+        float x = 0.f;
+        hipError_t e = hipEventSynchronize(tl.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&x, tl.a, tl.b);
+        if (e != hipSuccess && st == CUM_OK) st = fail(CUM_EHIP, "timing events: %s", hipGetErrorString(e));
+        ms[tl.kind] += x;
+        launches[tl.kind] += 1;
+        (void)hipEventDestroy(tl.a);
+        (void)hipEventDestroy(tl.b);
+    }
+    g_timed.clear();
+    return st;
+}
+
+struct cum_batch {
+    int dummy;
+};
+
+cum_status cum_batch_create(int, const int64_t *, int, int, int, cum_prec, cum_batch **) {
+    return fail(CUM_EUNSUPPORTED, "batched path not built yet");
+}
+cum_status cum_batch_run(cum_batch *, const double *const *, double *const *, double *const *, void *) {
+    return fail(CUM_EUNSUPPORTED, "batched path not built yet");
+}
+cum_status cum_batch_timestamps(cum_batch *, uint64_t *, uint64_t *, double *) {
+    return fail(CUM_EUNSUPPORTED, "batched path not built yet");
+}
+cum_status cum_batch_destroy(cum_batch *) { return CUM_OK; }
+
+}  // extern "C"

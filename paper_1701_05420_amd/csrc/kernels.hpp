@@ -1,0 +1,62 @@
+// Launch interface between the host planner and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.hpp"
+
+namespace cum {
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X2 = 2, P_BF16X3 = 3 };
+
+struct MomentArgs {
+    const OrderDev *ords;
+    const TileDev *tiles;
+    const Item *items;
+    int64_t nitems;
+    const SetDev *sets;  // per-dataset records, or null: every item uses set0
+    SetDev set0;
+    int32_t n;   // variables; LDS column / row n holds zeros
+    int32_t kt;  // samples per LDS stage, a multiple of 16
+};
+
+struct RedArgs {
+    const RedOrder *ords;  // the orders finalised by this launch (1 or 2)
+    int32_t nords;
+    int32_t recursion;  // 0: plain moments (no cumulant recursion)
+    int64_t nb0;   // blocks of the first order
+    int64_t nbtot; // blocks of all orders of the launch
+    const SetRed *sets;  // per-dataset records (grid.y), or null: set0
+    SetRed set0;
+};
+
+// Work-group tile shapes: WM x WN blocks of 32 x 32 per wave, 2 x 2 waves.
+enum TileShape { TS_1x1 = 0, TS_2x1 = 2 };
+
+int lds_bytes_moment(int prec, int n, int kt);
+hipError_t launch_moment(int prec, int shape, const MomentArgs &a, int grid, hipStream_t s);
+hipError_t launch_reduce(const RedArgs &a, int nsets, hipStream_t s);
+hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,
+                         hipStream_t s);
+hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s);
+hipError_t launch_center(const double *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xc, int prec,
+                         hipStream_t s);
+hipError_t launch_unfold(const double *blocks, int n, int d, int b, double *dense, hipStream_t s);
+
+// Batched centring: one launch for many datasets (same n).
+struct CenterSet {
+    const double *X;   // t x n, ld n
+    int64_t t;
+    double *mean;      // n
+    float *Xc;         // t x n FP32 (or double* when the precision is FP64)
+    double *part;      // groups x n x 2 partial sums
+    int32_t groups;
+    int32_t pad;
+    int64_t rows_per;
+};
+hipError_t launch_batch_colsum(const CenterSet *sets, int nsets, int max_groups, int n, hipStream_t s);
+hipError_t launch_batch_mean(const CenterSet *sets, int nsets, int n, hipStream_t s);
+hipError_t launch_batch_center(const CenterSet *sets, int nsets, int n, int prec, int blocks_per_set, hipStream_t s);
+hipError_t launch_stamp(unsigned long long *where, hipStream_t s);
+
+}  // namespace cum

@@ -1,0 +1,95 @@
+// Host planner and the device-visible records it builds.
+//
+// The order-d moment tensor over sorted block tuples (Alg. 1, Alg. 2) is
+// evaluated as one contraction per order: a tuple j_1 <= ... <= j_d is cut
+// into a prefix (j_1..j_p, p = floor(d/2)) and a suffix (j_{p+1}..j_d).
+// Rows enumerate (prefix tuple, in-block digits of the prefix), sorted by the
+// prefix's last block v; columns enumerate (suffix tuple, in-block digits of
+// the suffix), sorted by the suffix's first block w.  Entry (row, col) is a
+// stored moment entry exactly when v <= w, and then
+//   S[row, col] = sum_l  prod_{prefix vars} x_l  *  prod_{suffix vars} x_l ,
+// a matrix product over samples whose operands are Khatri-Rao products of
+// columns of X -- formed on the fly from samples staged in LDS, never stored.
+// The lexicographic rank of a sorted tuple splits into a prefix part, a term
+// that depends only on (v, w), and a suffix part, so the storage offset of
+// (row, col) is row.addr + col.addr + H[v][w].
+#pragma once
+
+#include <cstdint>
+#include <cstddef>
+
+namespace cum {
+
+constexpr int MAXD = 8;   // largest order
+constexpr int MAXH = 4;   // longest prefix / suffix = ceil(MAXD / 2)
+constexpr int MAXN = 255; // variables (index n is the zero column)
+constexpr int FEAT_BLOCK = 32;
+
+// One row (prefix) or column (suffix) of an order's contraction.
+struct Feat {
+    int64_t addr;          // row: rank part of the prefix * b^d + prefix digits * b^q
+                           // col: rank part of the suffix * b^d + suffix digits
+    int32_t blk;           // row: last prefix block v (INT32_MAX for padding rows)
+                           // col: first suffix block w (-1 for padding columns)
+    uint8_t var[MAXH];     // variable of each position (n = the zero column)
+};
+static_assert(sizeof(Feat) == 16, "Feat layout");
+
+// Everything a kernel needs to know about one order (device pointers).
+struct OrderDev {
+    const Feat *rows;
+    const Feat *cols;
+    const int32_t *rb_vmin;  // per 32-row block: smallest v of its real rows
+    const int32_t *cb_wmax;  // per 32-col block: largest w of its real columns
+    const int64_t *H;        // nbar x nbar: (v, w) term of the rank, times b^d
+    int64_t out_off;         // offset of this order in the per-chunk partial vector
+    int64_t elems;           // stored entries of this order
+    int32_t d, p, q, nbar, b, nr, nc, pad;
+};
+
+// A work-group tile of one order's contraction.
+struct TileDev {
+    int32_t ord;   // index into the OrderDev array
+    int32_t row0;
+    int32_t col0;
+    int32_t pad;
+};
+
+// One unit of the moment launch: a tile over one sample chunk of one dataset.
+struct Item {
+    int32_t tile;  // -1: no-op
+    int32_t chunk;
+    int32_t set;
+    int32_t pad;
+};
+
+// Per dataset: the (device-precision) centred data and its partial sums.
+struct SetDev {
+    const void *X;       // t x n, leading dimension n
+    int64_t t;
+    int64_t chunk_len;
+    int64_t nchunks;
+    double *partial;     // nchunks x stride
+    int64_t stride;      // stored entries of all orders 2..d_max
+};
+
+// Reduction / recursion records.
+constexpr int MAXPARTS = MAXD / 2;  // parts of size >= 2 in a partition of <= MAXD positions
+struct RedOrder {
+    const uint8_t *tuples;  // nblocks x d sorted block tuples (lexicographic order)
+    const uint16_t *parts;  // npart x MAXPARTS position masks (0 = unused)
+    int64_t nblocks;
+    int64_t out_off;        // offset of this order in the per-chunk partial vector
+    int32_t d, npart, nbar, b;
+};
+
+struct SetRed {
+    const double *partial;
+    int64_t stride;
+    int64_t nchunks;
+    int64_t t;
+    double *kappa[MAXD - 1];       // kappa[d-2]
+    unsigned long long *stamp;     // finalisation timestamp (or null)
+};
+
+}  // namespace cum

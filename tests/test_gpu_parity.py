@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances (normwise, e_d = max|gpu - oracle| / max|oracle| over the compared
+entries of order d):
+  * FP64 path: 1e-10, and bit-exact on small-integer data whose sums are exact;
+  * FP32 and BF16x3 paths: 1e-6, and bit-exact on small-integer data (every
+    product and partial sum is exactly representable there);
+  * BF16x2 path: 5e-5 (each Khatri-Rao operand is carried as two BF16 terms,
+    16 significant bits: a relative residual of up to 2^-18 per operand, which
+    near-cancelling entries such as the third cumulant of nearly symmetric
+    data amplify), and bit-exact on small-integer data.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["f64", "f32", "bf16x2", "bf16x3"]
+TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1701_05420_amd as pc
+
+    return torch, pc
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(got, want):
+    den = np.abs(want).max()
+    return np.abs(got - want).max() / (den if den > 0 else 1.0)
+
+
+def run_gpu(dev, X, d_max, b, prec):
+    torch, pc = dev
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    mean, K = pc.cumulants(Xd, d_max, b, prec)
+    torch.cuda.synchronize()
+    return mean.cpu().numpy(), {d: K[d].cpu().numpy() for d in K}
+
+
+def stored_sample(orc, n, d, b, count, seed):
+    """Random stored offsets plus every pure-diagonal entry, padding dropped."""
+    import paper_1701_05420_amd as pc
+
+    elems = pc.layout(n, d, b)["elems"]
+    rng = np.random.default_rng(seed)
+    offs = rng.choice(elems, size=min(count, elems), replace=False)
+    diag = [pc.stored_offset(n, d, b, [i] * d) for i in range(n)]
+    offs = np.unique(np.concatenate([offs, diag]))
+    idx = orc.block_indices(n, d, b, offs)
+    keep = idx[:, 0] >= 0
+    return offs[keep], idx[keep]
+
+
+# ---------------------------------------------------------------- exact data
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,b,shift", [(6, 4, 0.0), (5, 2, 3.0), (9, 3, -2.0)])
+def test_integer_data_bit_exact(dev, orc, prec, n, b, shift):
+    say(f"integer bit-exact prec={prec} n={n} b={b} shift={shift}")
+    X = workloads.dyadic_integers(t=256, n=n, seed=n + b, lo=-2, hi=2) + shift
+    mean, K = run_gpu(dev, X, 6, b, prec)
+    omean, OK = orc.cumulants_dense(X, 6)
+    assert np.array_equal(mean, omean)
+    for d in range(2, 7):
+        want = orc.fold(OK[d], b)
+        assert np.array_equal(K[d], want), (d, np.abs(K[d] - want).max())
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_unfold_integer_exact(dev, orc, prec):
+    torch, pc = dev
+    say(f"unfold prec={prec}")
+    X = workloads.dyadic_integers(t=128, n=7, seed=3, lo=-2, hi=2)
+    _, OK = orc.cumulants_dense(X, 5)
+    Xd = torch.from_numpy(X).cuda()
+    _, K = pc.cumulants(Xd, 5, 3, prec)
+    for d in range(2, 6):
+        dense = pc.unfold(K[d], 7, d, 3).cpu().numpy()
+        assert np.array_equal(dense, OK[d]), d
+
+
+# ---------------------------------------------------------------- small dense
+@pytest.mark.parametrize("prec", PRECS)
+def test_t_wishart_n16_dense(dev, orc, prec):
+    say(f"t-wishart n16 t5000 dense prec={prec}")
+    X = workloads.generate("t-wishart-n16-t5000")
+    mean, K = run_gpu(dev, X, 4, 2, prec)
+    omean, OK = orc.cumulants_dense(X, 4)
+    assert np.abs(mean - omean).max() <= 1e-14 * np.abs(X).max()
+    for d in range(2, 5):
+        e = rel(K[d], orc.fold(OK[d], 2))
+        say(f"  e_{d} = {e:.3e}")
+        assert e <= TOL[prec], (d, e)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,b,t,dmax", [(7, 3, 3000, 6), (11, 4, 2000, 5), (13, 13, 1500, 4), (9, 1, 1000, 4)])
+def test_ragged_small_dense(dev, orc, prec, n, b, t, dmax):
+    say(f"ragged dense prec={prec} n={n} b={b} t={t} dmax={dmax}")
+    X = workloads.t_gamma_mix(t=t, n=n, seed=n * 7 + b)
+    mean, K = run_gpu(dev, X, dmax, b, prec)
+    _, OK = orc.cumulants_dense(X, dmax)
+    for d in range(2, dmax + 1):
+        e = rel(K[d], orc.fold(OK[d], b))
+        say(f"  e_{d} = {e:.3e}")
+        assert e <= TOL[prec], (d, e)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_moment_blocks_multi_tile_sampled(dev, orc, prec):
+    """n = 37, b = 5: several work-group tiles per order and a ragged block."""
+    torch, pc = dev
+    n, b, t = 37, 5, 4000
+    say(f"moment_blocks n={n} b={b} t={t} prec={prec}")
+    X = workloads.laplace_mix(t=t, n=n, seed=5)
+    _, Xc = orc.center(X)
+    Xd = torch.from_numpy(Xc).cuda()
+    if prec != "f64":
+        Xd = Xd.float()
+    for d in range(2, 6):
+        M = pc.moment_blocks(Xd, d, b, prec).cpu().numpy()
+        offs, idx = stored_sample(orc, n, d, b, 400, seed=d)
+        want = np.array([np.mean(np.prod(Xc[:, ix], axis=1)) for ix in idx])
+        e = rel(M[offs], want)
+        say(f"  moment e_{d} = {e:.3e}")
+        assert e <= TOL[prec], (d, e)
+
+
+# ---------------------------------------------------------------- properties
+def test_deterministic_and_shift_invariant(dev):
+    X = workloads.t_gamma_mix(t=20_000, n=20, seed=1)
+    for prec in PRECS:
+        say(f"determinism prec={prec}")
+        _, K1 = run_gpu(dev, X, 5, 4, prec)
+        _, K2 = run_gpu(dev, X, 5, 4, prec)
+        for d in K1:
+            assert np.array_equal(K1[d], K2[d]), (prec, d)
+    _, Ka = run_gpu(dev, X, 5, 4, "f64")
+    _, Kb = run_gpu(dev, X + 1000.0, 5, 4, "f64")
+    for d in Ka:
+        assert rel(Kb[d], Ka[d]) < 1e-7, d
+
+
+def test_edge_cases(dev, orc):
+    torch, pc = dev
+    say("edge cases")
+    # t = 1: centred data are all zero
+    X = np.array([[1.5, -2.0, 3.25]])
+    _, K = run_gpu(dev, X, 4, 2, "f64")
+    for d in K:
+        assert not np.any(K[d])
+    # d_max = 2 is the biased covariance
+    X = workloads.t_wishart(t=777, n=5, seed=4)
+    _, K = run_gpu(dev, X, 2, 5, "f64")
+    C = np.cov(X, rowvar=False, bias=True)
+    assert rel(K[2], C.reshape(-1)) < 1e-12
+    # one variable, one-element blocks
+    x = workloads.laplace_mix(t=5000, n=1, seed=2)
+    _, K = run_gpu(dev, x, 6, 1, "f64")
+    _, OK = orc.cumulants_dense(x, 6)
+    for d in range(2, 7):
+        assert abs(K[d][0] - OK[d].reshape(-1)[0]) <= 1e-10 * abs(OK[d].reshape(-1)[0])
+    # workspace too small is refused before anything runs
+    Xd = torch.from_numpy(X).cuda()
+    ws = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(pc.CumulantError):
+        pc.cumulants(Xd, 4, 2, "f64", ws=ws)
+
+
+def test_center_entry_point(dev, orc):
+    torch, pc = dev
+    X = workloads.ar1_garch(t=3000, n=9, seed=3) + 50.0
+    for prec in ["f64", "f32"]:
+        mean, Xc = pc.center(torch.from_numpy(X).cuda(), prec)
+        om, oXc = orc.center(X)
+        assert np.abs(mean.cpu().numpy() - om).max() <= 1e-15 * np.abs(om).max()
+        got = Xc.cpu().numpy().astype(np.float64)
+        want = oXc if prec == "f64" else oXc.astype(np.float32).astype(np.float64)
+        tol = 1e-13 if prec == "f64" else 1.2e-7
+        assert np.abs(got - want).max() <= tol * np.abs(oXc).max()
