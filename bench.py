@@ -44,8 +44,9 @@ def alg_flops(pc, t, n, d_max, b):
     return sum(2.0 * t * pc.layout(n, d, b)["elems"] for d in range(2, d_max + 1))
 
 
-def time_path(torch, pc, Xd, d_max, b, prec, steps, warmup):
+def time_path(torch, pc, Xd, d_max, b, prec, steps, warmup, tune):
     t, n = Xd.shape
+    tuned = pc.autotune(Xd, d_max, b, prec) if tune else None
     out = {d: torch.empty(pc.layout(n, d, b)["elems"], dtype=torch.float64, device="cuda")
            for d in range(2, d_max + 1)}
     ws = torch.empty(pc.workspace_size(t, n, d_max, b, prec), dtype=torch.uint8, device="cuda")
@@ -65,7 +66,7 @@ def time_path(torch, pc, Xd, d_max, b, prec, steps, warmup):
     kinds = pc.timing_read()
     pc.timing_enable(False)
     torch.cuda.synchronize()
-    return wall, kinds, out
+    return wall, kinds, out, tuned
 
 
 def sampled_errors(orc, pc, X, kappa, n, d_max, b, count=300, seed=7):
@@ -132,6 +133,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (planner defaults)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -161,14 +163,15 @@ def main():
     res, kappa = {}, {}
     for p in precs:
         log(f"timing {p}")
-        wall, kinds, out = time_path(torch, pc, Xd, d_max, b, p, args.steps, args.warmup)
+        wall, kinds, out, tuned = time_path(torch, pc, Xd, d_max, b, p, args.steps, args.warmup, not args.no_tune)
         mom_ms, mom_n = kinds["moment"]
         per_launch = mom_ms / max(mom_n, 1)
         achieved = flops / (per_launch * 1e-3) / 1e12
         res[p] = {"ms_per_step": wall * 1e3, "tflops": flops / wall / 1e12,
                   "moment_ms_per_launch": per_launch, "moment_tflops": achieved,
                   "mfma_frac": achieved * PRODUCTS[p] / PEAK[p],
-                  "kernel_ms": {k: v[0] / args.steps for k, v in kinds.items() if v[1]}}
+                  "kernel_ms": {k: v[0] / args.steps for k, v in kinds.items() if v[1]},
+                  "tuning": tuned}
         kappa[p] = {d: out[d].cpu().numpy() for d in out}
         log(f"  {p}: {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s; "
             f"moment kernel {per_launch:.3f} ms = {achieved:.2f} TFLOP/s")

@@ -74,7 +74,7 @@ typedef enum {
                     /* most 64 samples, then FP64                               */
     CUM_BF16X2 = 2, /* FP32 data; each half-product split into two BF16 terms, */
                     /* all 4 cross products on BF16 matrix cores, FP32 sums    */
-                    /* over at most 256 samples, then FP64                      */
+                    /* over at most 64 samples, then FP64                       */
     CUM_BF16X3 = 3  /* as BF16X2 with a three-term split and the 6 cross       */
                     /* products of combined weight >= 2^-16                     */
 } cum_prec;
@@ -182,6 +182,38 @@ cum_status cum_batch_destroy(cum_batch *plan);
  * every stored entry exactly once (no GPU needed).  Returns CUM_OK or
  * CUM_EINVAL with a message. */
 cum_status cum_plan_check(int n, int d, int b);
+
+/* ------------------------------------------------------------------------
+ * Autotuning of the contraction's launch shape (the paper picks its block
+ * size b by timing, Section 5.2; here b is the caller's storage choice and
+ * the tuned knobs are the launch's):
+ *   shape         work-group tile of one order's (rows x columns) product:
+ *                 0 = 64 x 64, 2 = 128 x 64, 1 = 128 x 128 entries;
+ *   target_items  about how many (tile, sample-chunk) work items to create;
+ *                 it sets the sample chunk length, hence the split over
+ *                 samples and the size of the FP64 partial-sum buffer.
+ * A tuned choice applies to later calls with the same (t, n, d_max, b, prec)
+ * and changes their workspace size: query cum_workspace_size afterwards.
+ * With the environment variable CUM_TUNE_FILE set, choices are also read
+ * from and written to that file (one line per shape).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t shape;
+    int32_t target_items;
+    float ms;  /* autotune: measured time of the chosen configuration */
+} cum_tuning;
+
+/* Time every candidate configuration of cum_cumulants(t, n, d_max, b, prec)
+ * on the caller's data X (t x n FP64, ld ldx, device) -- contraction plus
+ * reduction and recursion, best of three after a warm-up, HIP events on
+ * stream -- and keep the fastest.  Allocates and frees its own device
+ * workspace; synchronises stream.  best (host) may be NULL. */
+cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
+                        void *stream, cum_tuning *best /* host */);
+
+/* Host only.  Set (tune != NULL) or forget (tune == NULL) the configuration
+ * used for cum_cumulants(t, n, d_max, b, prec). */
+cum_status cum_set_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, const cum_tuning *tune /* host */);
 
 /* Host only.  Measurement helpers.  While enabled on the calling thread,
  * every kernel launch made by the entry points on that thread is bracketed by

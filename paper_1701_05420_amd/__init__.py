@@ -31,8 +31,14 @@ MAX_ORDER = 8
 EXPORTS = [
     "cum_layout_query", "cum_workspace_size", "cum_center", "cum_moment_blocks", "cum_cumulants", "cum_unfold",
     "cum_stored_offset", "cum_batch_create", "cum_batch_run", "cum_batch_timestamps", "cum_batch_destroy",
-    "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_status_str", "cum_last_error",
+    "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning", "cum_status_str",
+    "cum_last_error",
 ]
+SHAPES = {"64x64": 0, "128x128": 1, "128x64": 2}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("target_items", ctypes.c_int32), ("ms", ctypes.c_float)]
 KINDS = ["center", "moment", "reduce", "unfold", "batch"]
 
 
@@ -57,6 +63,8 @@ _lib.cum_batch_timestamps.argtypes = [_VP, ctypes.POINTER(ctypes.c_uint64), ctyp
 _lib.cum_batch_destroy.argtypes = [_VP]
 _lib.cum_plan_check.argtypes = [_I, _I, _I]
 _lib.cum_timing_enable.argtypes = [_I]
+_lib.cum_autotune.argtypes = [_VP, _I64, _I, _I64, _I, _I, _I, _VP, ctypes.POINTER(Tuning)]
+_lib.cum_set_tuning.argtypes = [_I64, _I, _I, _I, _I, ctypes.POINTER(Tuning)]
 _lib.cum_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]
 _lib.cum_status_str.argtypes = [_I]
 _lib.cum_status_str.restype = ctypes.c_char_p
@@ -107,6 +115,26 @@ def stored_offset(n: int, d: int, b: int, idx) -> int:
 
 def plan_check(n: int, d: int, b: int) -> None:
     _check(_lib.cum_plan_check(n, d, b))
+
+
+def autotune(X, d_max: int, b: int, prec="f32", stream=None) -> dict:
+    """Time the launch configurations on X and keep the fastest for this shape."""
+    torch = _torch()
+    _dev_check(X, torch.float64, "X")
+    t, n = X.shape
+    out = Tuning()
+    _check(_lib.cum_autotune(X.data_ptr(), t, n, X.stride(0), d_max, b, _prec(prec), _stream(stream),
+                             ctypes.byref(out)))
+    return {"shape": out.shape, "target_items": out.target_items, "ms": out.ms}
+
+
+def set_tuning(t: int, n: int, d_max: int, b: int, prec, shape=None, target_items=1024) -> None:
+    """Fix the launch configuration for a shape (shape=None forgets it)."""
+    if shape is None:
+        _check(_lib.cum_set_tuning(t, n, d_max, b, _prec(prec), None))
+        return
+    tune = Tuning(SHAPES[shape] if isinstance(shape, str) else int(shape), int(target_items), 0.0)
+    _check(_lib.cum_set_tuning(t, n, d_max, b, _prec(prec), ctypes.byref(tune)))
 
 
 def timing_enable(on: bool = True) -> None:

@@ -343,8 +343,8 @@ static void order_tiles(const OrderPlan &o, int wm, int wn, int ord_index, std::
 }
 
 static void shape_dims(int shape, int &wm, int &wn) {
-    wm = shape == TS_2x1 ? 2 : 1;
-    wn = 1;
+    wm = (shape == TS_2x1 || shape == TS_2x2) ? 2 : 1;
+    wn = shape == TS_2x2 ? 2 : 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -352,8 +352,8 @@ static void shape_dims(int shape, int &wm, int &wn) {
 // one sample count.
 // ---------------------------------------------------------------------------
 struct CallPlan {
-    int n = 0, b = 0, dlo = 0, dhi = 0, prec = 0, shape = 0, kt = 0;
-    int64_t t = 0, chunk_len = 0, nchunks = 0, stride = 0, nitems = 0;
+    int n = 0, b = 0, dlo = 0, dhi = 0, prec = 0, shape = 0;
+    int64_t t = 0, nstages = 0, chunk_stages = 0, nchunks = 0, stride = 0, nitems = 0;
     std::vector<OrderPlan *> orders;  // index d - dlo
     std::vector<int64_t> out_off;     // index d - dlo
     std::vector<OrderDev> ods;
@@ -387,18 +387,55 @@ static cum_status upload_call(CallPlan &c) {
     return CUM_OK;
 }
 
-static std::map<std::tuple<int, int, int, int, int, int, int64_t>, std::unique_ptr<CallPlan>> g_calls;
+static std::map<std::tuple<int, int, int, int, int, int, int, int64_t>, std::unique_ptr<CallPlan>> g_calls;
 
-static int choose_kt(int prec, int n) {
-    int kt = (16 * 256 / n) / 16 * 16;
-    int ktmax = prec == P_F64 ? 32 : (prec == P_F32 ? 64 : 128);
-    return std::max(16, std::min(kt, ktmax));
+// Tuned choices: (n, b, dlo, dhi, prec, t) -> (shape, target items).
+struct Tuning {
+    int shape;
+    int target;
+};
+static std::map<std::tuple<int, int, int, int, int, int64_t>, Tuning> g_tuned;
+static bool g_tune_loaded = false;
+
+static const char *tune_file() {
+    const char *f = getenv("CUM_TUNE_FILE");
+    return (f && *f) ? f : nullptr;
 }
 
-static int default_shape(int prec) { return prec == P_F64 ? TS_1x1 : TS_2x1; }
+// Cache file: one line per tuned shape, "n b dlo dhi prec t shape target".
+static void load_tune_file() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *f = tune_file();
+    if (!f) return;
+    FILE *fp = fopen(f, "r");
+    if (!fp) return;
+    int n, b, dlo, dhi, prec, shape, target;
+    long long t;
+    while (fscanf(fp, "%d %d %d %d %d %lld %d %d", &n, &b, &dlo, &dhi, &prec, &t, &shape, &target) == 8)
+        g_tuned[std::make_tuple(n, b, dlo, dhi, prec, (int64_t)t)] = Tuning{shape, target};
+    fclose(fp);
+}
 
-static cum_status get_call(int n, int b, int dlo, int dhi, int prec, int shape, int64_t t, CallPlan **out) {
-    auto key = std::make_tuple(n, b, dlo, dhi, prec, shape, t);
+static void save_tune_file() {
+    const char *f = tune_file();
+    if (!f) return;
+    FILE *fp = fopen(f, "w");
+    if (!fp) return;
+    for (auto &kv : g_tuned) {
+        auto &k = kv.first;
+        fprintf(fp, "%d %d %d %d %d %lld %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                std::get<4>(k), (long long)std::get<5>(k), kv.second.shape, kv.second.target);
+    }
+    fclose(fp);
+}
+
+static int default_shape(int prec) { return prec == P_F32 ? TS_1x1 : TS_2x1; }
+constexpr int DEFAULT_TARGET = 1024;
+
+static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int shape, int target, int64_t t,
+                               CallPlan **out) {
+    auto key = std::make_tuple(n, b, dlo, dhi, prec, shape, target, t);
     auto it = g_calls.find(key);
     if (it != g_calls.end()) {
         *out = it->second.get();
@@ -412,7 +449,7 @@ static cum_status get_call(int n, int b, int dlo, int dhi, int prec, int shape, 
     c->prec = prec;
     c->shape = shape;
     c->t = t;
-    c->kt = choose_kt(prec, n);
+    c->nstages = (t + stage_kt(prec) - 1) / stage_kt(prec);
     int wm, wn;
     shape_dims(shape, wm, wn);
     std::vector<HostTile> tiles;
@@ -457,13 +494,14 @@ static cum_status get_call(int n, int b, int dlo, int dhi, int prec, int shape, 
     // expensive tiles first, so that the tail of each XCD's queue is short
     std::stable_sort(tiles.begin(), tiles.end(), [](const HostTile &x, const HostTile &y) { return x.cost > y.cost; });
     const int64_t ntiles = (int64_t)tiles.size();
-    // sample chunks: enough items to fill 256 CUs twice over, chunks of >= 256 samples
-    int64_t want = (1024 + ntiles - 1) / ntiles;
-    int64_t maxch = std::max<int64_t>(1, t / 256);
+    // sample chunks (whole stages): about `target` work items (1024 fills the
+    // 256 CUs twice over with two work-groups each), chunks of >= 4 stages
+    int64_t want = (target + ntiles - 1) / ntiles;
+    int64_t maxch = std::max<int64_t>(1, c->nstages / 4);
     int64_t nch = std::max<int64_t>(1, std::min(want, maxch));
     if (nch >= 8) nch = (nch + 7) / 8 * 8;
-    c->chunk_len = (t + nch - 1) / nch;
-    c->nchunks = (t + c->chunk_len - 1) / c->chunk_len;
+    c->chunk_stages = (c->nstages + nch - 1) / nch;
+    c->nchunks = (c->nstages + c->chunk_stages - 1) / c->chunk_stages;
     // items: chunk ch is processed on XCD (ch % 8); WG i runs on XCD (i % 8)
     std::vector<std::vector<Item>> per_xcd(8);
     for (int64_t ch = 0; ch < c->nchunks; ++ch)
@@ -482,6 +520,14 @@ static cum_status get_call(int n, int b, int dlo, int dhi, int prec, int shape, 
     return CUM_OK;
 }
 
+// The call plan for a shape: the tuned choice if there is one, else the defaults.
+static cum_status get_call(int n, int b, int dlo, int dhi, int prec, int64_t t, CallPlan **out) {
+    load_tune_file();
+    auto it = g_tuned.find(std::make_tuple(n, b, dlo, dhi, prec, t));
+    if (it != g_tuned.end()) return get_call_cfg(n, b, dlo, dhi, prec, it->second.shape, it->second.target, t, out);
+    return get_call_cfg(n, b, dlo, dhi, prec, default_shape(prec), DEFAULT_TARGET, t, out);
+}
+
 static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
 static void center_groups(int64_t t, int &groups, int64_t &rows_per) {
@@ -491,7 +537,10 @@ static void center_groups(int64_t t, int &groups, int64_t &rows_per) {
     groups = (int)((t + rows_per - 1) / rows_per);
 }
 
-static int esize(int prec) { return prec == P_F64 ? 8 : 4; }
+static size_t staged_bytes(int64_t t, int n, int prec) {
+    const int64_t nst = (t + stage_kt(prec) - 1) / stage_kt(prec);
+    return align_up((size_t)nst * (n + 1) * stage_pitch(prec) * stage_esize(prec));
+}
 
 static cum_status check_common(int64_t t, int n, int b) {
     if (t < 1) return fail(CUM_EINVAL, "t must be >= 1 (got %lld)", (long long)t);
@@ -518,13 +567,13 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
     ma.nitems = c->nitems;
     ma.sets = nullptr;
     ma.set0.X = Xc;
-    ma.set0.t = c->t;
-    ma.set0.chunk_len = c->chunk_len;
+    ma.set0.nstages = c->nstages;
+    ma.set0.chunk_stages = c->chunk_stages;
     ma.set0.nchunks = c->nchunks;
     ma.set0.partial = partial;
     ma.set0.stride = c->stride;
     ma.n = c->n;
-    ma.kt = c->kt;
+    ma.pad = 0;
     if (c->nitems > 0)
         HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, ma, (int)c->nitems, s); }));
     // reduction (+ recursion) in pairs of orders {d, d+1}: order d needs
@@ -631,14 +680,14 @@ cum_status cum_workspace_size(int64_t t, int n, int d_max, int b, cum_prec prec,
     int groups;
     int64_t rows_per;
     center_groups(t, groups, rows_per);
-    size_t total = align_up((size_t)t * n * esize(prec)) + align_up((size_t)groups * n * 2 * 8) + align_up((size_t)n * 8);
+    size_t total = staged_bytes(t, n, prec) + align_up((size_t)groups * n * 2 * 8) + align_up((size_t)n * 8);
     CallPlan *c;
-    if ((st = get_call(n, b, 2, d_max, prec, default_shape(prec), t, &c))) return st;
+    if ((st = get_call(n, b, 2, d_max, prec, t, &c))) return st;
     size_t part = (size_t)c->nchunks * c->stride * 8;
     // a single-order moment call uses its own plan; cover the largest one
     for (int d = 2; d <= d_max; ++d) {
         CallPlan *c1;
-        if ((st = get_call(n, b, d, d, prec, default_shape(prec), t, &c1))) return st;
+        if ((st = get_call(n, b, d, d, prec, t, &c1))) return st;
         part = std::max(part, (size_t)c1->nchunks * c1->stride * 8);
     }
     *bytes = total + align_up(part);
@@ -676,11 +725,18 @@ cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, in
     if (!Xc || !M) return fail(CUM_EINVAL, "Xc and M must not be NULL");
     std::lock_guard<std::mutex> lk(g_mu);
     CallPlan *c;
-    if ((st = get_call(n, b, d, d, prec, default_shape(prec), t, &c))) return st;
-    size_t need = align_up((size_t)c->nchunks * c->stride * 8);
+    if ((st = get_call(n, b, d, d, prec, t, &c))) return st;
+    const size_t xbytes = staged_bytes(t, n, prec);
+    const size_t need = xbytes + align_up((size_t)c->nchunks * c->stride * 8);
     if (!ws || ws_bytes < need) return fail(CUM_ENOMEM, "moment_blocks needs %zu workspace bytes", need);
+    if ((st = upload_call(*c))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *Xst = (char *)ws;
+    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] {
+        return launch_stage(Xc, t, n, n, nullptr, Xst, prec, false, prec == P_F64, s);
+    }));
     double *outs[1] = {M};
-    return run_orders(c, Xc, (double *)ws, outs, false, (hipStream_t)stream);
+    return run_orders(c, Xst, (double *)(Xst + xbytes), outs, false, s);
 }
 
 cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
@@ -694,24 +750,27 @@ cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_m
         if (!kappa[d - 2]) return fail(CUM_EINVAL, "kappa[%d] is NULL", d - 2);
     std::lock_guard<std::mutex> lk(g_mu);
     CallPlan *c;
-    if ((st = get_call(n, b, 2, d_max, prec, default_shape(prec), t, &c))) return st;
+    if ((st = get_call(n, b, 2, d_max, prec, t, &c))) return st;
     int groups;
     int64_t rows_per;
     center_groups(t, groups, rows_per);
-    const size_t xbytes = align_up((size_t)t * n * esize(prec));
+    const size_t xbytes = staged_bytes(t, n, prec);
     const size_t cbytes = align_up((size_t)groups * n * 2 * 8);
     const size_t mbytes = align_up((size_t)n * 8);
     const size_t pbytes = align_up((size_t)c->nchunks * c->stride * 8);
     const size_t need = xbytes + cbytes + mbytes + pbytes;
     if (!ws || ws_bytes < need) return fail(CUM_ENOMEM, "cumulants needs %zu workspace bytes (got %zu)", need, ws_bytes);
     char *w = (char *)ws;
-    void *Xc = w;
+    char *Xst = w;
     char *cw = w + xbytes;
     double *mtmp = (double *)(w + xbytes + cbytes);
     double *partial = (double *)(w + xbytes + cbytes + mbytes);
     hipStream_t s = (hipStream_t)stream;
-    if ((st = center_impl(X, t, n, ldx, prec, mean ? mean : mtmp, Xc, cw, cbytes, s))) return st;
-    return run_orders(c, Xc, partial, kappa, true, s);
+    double *mu = mean ? mean : mtmp;
+    if ((st = upload_call(*c))) return st;
+    if ((st = center_impl(X, t, n, ldx, prec, mu, nullptr, cw, cbytes, s))) return st;
+    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, mu, Xst, prec, true, true, s); }));
+    return run_orders(c, Xst, partial, kappa, true, s);
 }
 
 cum_status cum_unfold(const double *blocks, int n, int d, int b, double *dense, void *stream) {
@@ -732,7 +791,7 @@ cum_status cum_plan_check(int n, int d, int b) {
     if ((st = build_order(n, b, d, o))) return st;  // host tables only, nothing uploaded
     const int64_t be = ipow64(b, d);
     auto T = sorted_tuples(o.nbar, d);
-    for (int shape : {TS_1x1, TS_2x1}) {
+    for (int shape : {TS_1x1, TS_2x1, TS_2x2}) {
         int wm, wn;
         shape_dims(shape, wm, wn);
         std::vector<HostTile> tiles;
@@ -770,6 +829,104 @@ cum_status cum_plan_check(int n, int d, int b) {
         }
         for (size_t e = 0; e < hits.size(); ++e)
             if (hits[e] != 1) return fail(CUM_EINVAL, "d=%d: address %zu never written", d, e);
+    }
+    return CUM_OK;
+}
+
+cum_status cum_set_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, const cum_tuning *tune) {
+    cum_status st;
+    if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;
+    if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_tune_file();
+    auto key = std::make_tuple(n, b, 2, d_max, (int)prec, t);
+    if (!tune) {
+        g_tuned.erase(key);
+        return CUM_OK;
+    }
+    if (tune->shape != TS_1x1 && tune->shape != TS_2x1 && tune->shape != TS_2x2)
+        return fail(CUM_EINVAL, "unknown tile shape %d", tune->shape);
+    if (tune->target_items < 1) return fail(CUM_EINVAL, "target_items must be >= 1");
+    g_tuned[key] = Tuning{tune->shape, tune->target_items};
+    return CUM_OK;
+}
+
+// Time every candidate (tile shape x work-item target) on the caller's data
+// and keep the fastest for this shape: the contraction plus the reduction and
+// recursion, best of three after one warm-up, HIP events on the stream.
+cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec, void *stream,
+                        cum_tuning *best) {
+    cum_status st;
+    if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;
+    if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
+    if (!X || ldx < n) return fail(CUM_EINVAL, "bad X / ldx");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    const int shapes[] = {TS_1x1, TS_2x1};
+    const int targets[] = {512, 1024, 2048, 4096};
+    std::vector<CallPlan *> cands;
+    size_t part_max = 0;
+    for (int sh : shapes)
+        for (int tg : targets) {
+            CallPlan *c;
+            if ((st = get_call_cfg(n, b, 2, d_max, prec, sh, tg, t, &c))) return st;
+            if ((st = upload_call(*c))) return st;
+            cands.push_back(c);
+            part_max = std::max(part_max, align_up((size_t)c->nchunks * c->stride * 8));
+        }
+    int groups;
+    int64_t rows_per;
+    center_groups(t, groups, rows_per);
+    const size_t xbytes = staged_bytes(t, n, prec), cbytes = align_up((size_t)groups * n * 2 * 8);
+    const size_t mbytes = align_up((size_t)n * 8), kbytes = align_up((size_t)cands[0]->stride * 8);
+    DevBuf ws;
+    HIP_TRY(hipMalloc(&ws.p, xbytes + cbytes + mbytes + kbytes + part_max));
+    char *w = (char *)ws.p;
+    char *Xst = w, *cw = w + xbytes;
+    double *mu = (double *)(w + xbytes + cbytes), *kap = (double *)(w + xbytes + cbytes + mbytes);
+    double *partial = (double *)(w + xbytes + cbytes + mbytes + kbytes);
+    double *outs[CUM_MAX_ORDER];
+    for (int d = 2; d <= d_max; ++d) outs[d - 2] = kap + cands[0]->out_off[d - 2];
+    if ((st = center_impl(X, t, n, ldx, prec, mu, nullptr, cw, cbytes, s))) return st;
+    HIP_TRY(launch_stage(X, t, n, ldx, mu, Xst, prec, true, true, s));
+    const bool was_timing = g_timing;
+    g_timing = false;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    CallPlan *best_c = nullptr;
+    for (CallPlan *c : cands) {
+        float cand_ms = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+            HIP_TRY(hipEventRecord(e0, s));
+            if ((st = run_orders(c, Xst, partial, outs, true, s))) break;
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) cand_ms = std::min(cand_ms, ms);
+        }
+        if (st) break;
+        if (cand_ms < best_ms) {
+            best_ms = cand_ms;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_timing = was_timing;
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    int best_target = 0;
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (cands[i] == best_c) best_target = targets[i % 4];
+    g_tuned[std::make_tuple(n, b, 2, d_max, (int)prec, t)] = Tuning{best_c->shape, best_target};
+    save_tune_file();
+    if (best) {
+        best->shape = best_c->shape;
+        best->target_items = best_target;
+        best->ms = best_ms;
     }
     return CUM_OK;
 }

@@ -2,6 +2,7 @@
 // fixed-order chunk reduction fused with the cumulant recursion, unfold.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 
@@ -86,20 +87,32 @@ __global__ __launch_bounds__(256) void colsum_kernel(const double *X, int64_t t,
     colsum_body(X, t, n, ldx, rows_per, blockIdx.x, part);
 }
 
-__device__ __forceinline__ void mean_body(const double *part, int groups, int n, int64_t t, double *mean) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double S = 0.0, C = 0.0;
-        for (int g = 0; g < groups; ++g) {
-            neumaier(S, C, part[((int64_t)g * n + i) * 2]);
-            neumaier(S, C, part[((int64_t)g * n + i) * 2 + 1]);
+// One work-group per column: thread k sums groups k, k+256, ...; the 256
+// compensated partials are then combined in thread order.
+__device__ __forceinline__ void mean_body(const double *part, int groups, int n, int64_t t, double *mean, int i) {
+    __shared__ double ss[256], cs[256];
+    const int tid = threadIdx.x;
+    double S = 0.0, C = 0.0;
+    for (int g = tid; g < groups; g += 256) {
+        neumaier(S, C, part[((int64_t)g * n + i) * 2]);
+        neumaier(S, C, part[((int64_t)g * n + i) * 2 + 1]);
+    }
+    ss[tid] = S;
+    cs[tid] = C;
+    __syncthreads();
+    if (tid == 0) {
+        double S2 = 0.0, C2 = 0.0;
+        for (int k = 0; k < 256; ++k) {
+            neumaier(S2, C2, ss[k]);
+            neumaier(S2, C2, cs[k]);
         }
-        mean[i] = (S + C) / (double)t;
+        mean[i] = (S2 + C2) / (double)t;
     }
 }
 
 __global__ __launch_bounds__(256) void mean_kernel(const double *part, int groups, int n, int64_t t,
                                                    double *mean) {
-    mean_body(part, groups, n, t, mean);
+    mean_body(part, groups, n, t, mean, blockIdx.x);
 }
 
 template <typename T>
@@ -120,8 +133,8 @@ __global__ __launch_bounds__(256) void batch_colsum_kernel(const CenterSet *sets
 }
 
 __global__ __launch_bounds__(256) void batch_mean_kernel(const CenterSet *sets, int n) {
-    const CenterSet cs = sets[blockIdx.x];
-    mean_body(cs.part, cs.groups, n, cs.t, cs.mean);
+    const CenterSet cs = sets[blockIdx.y];
+    mean_body(cs.part, cs.groups, n, cs.t, cs.mean, blockIdx.x);
 }
 
 template <typename T>
@@ -141,15 +154,82 @@ __global__ void stamp_kernel(unsigned long long *where) {
 }
 
 // ---------------------------------------------------------------------------
+// Staged layout writers: row-major data -> the staged layout of plan.hpp.
+// One work-group per stage; variables are moved through LDS in groups of 32
+// so that both the row-major reads and the stage writes are contiguous.
+// ---------------------------------------------------------------------------
+template <typename TI, typename TO, bool CENTER>
+__device__ __forceinline__ void stage_body(const TI *X, int64_t t, int n, int64_t ldx, const double *mean, TO *Xst,
+                                           int KT, int KTP, int64_t s) {
+    __shared__ double tile[64][33];
+    const int tid = threadIdx.x;
+    const int64_t l0 = s * KT;
+    TO *dst = Xst + s * (int64_t)(n + 1) * KTP;
+    for (int v0 = 0; v0 <= n; v0 += 32) {
+        __syncthreads();
+        for (int e = tid; e < KT * 32; e += 256) {
+            const int k = e >> 5, v = v0 + (e & 31);
+            double x = 0.0;
+            if (v < n && l0 + k < t) {
+                x = (double)X[(l0 + k) * ldx + v];
+                if (CENTER) x -= mean[v];
+            }
+            tile[k][e & 31] = x;
+        }
+        __syncthreads();
+        const int nv = min(32, n + 1 - v0);
+        for (int e = tid; e < nv * KTP; e += 256) {
+            const int vv = e / KTP, k = e - vv * KTP;
+            dst[(int64_t)(v0 + vv) * KTP + k] = (k < KT) ? (TO)tile[k][vv] : TO(0);
+        }
+    }
+}
+
+template <typename TI, typename TO, bool CENTER>
+__global__ __launch_bounds__(256) void stage_kernel(const TI *X, int64_t t, int n, int64_t ldx, const double *mean,
+                                                    TO *Xst, int KT, int KTP, int64_t nstages) {
+    for (int64_t s = blockIdx.x; s < nstages; s += gridDim.x) stage_body<TI, TO, CENTER>(X, t, n, ldx, mean, Xst, KT, KTP, s);
+}
+
+hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xst, int prec,
+                        bool center, bool in_f64, hipStream_t s) {
+    const int KT = stage_kt(prec), KTP = stage_pitch(prec);
+    const int64_t nst = (t + KT - 1) / KT;
+    const unsigned grid = (unsigned)std::min<int64_t>(nst, 65535);
+    if (center) {
+        if (prec == P_F64)
+            hipLaunchKernelGGL((stage_kernel<double, double, true>), dim3(grid), dim3(256), 0, s, (const double *)X, t,
+                               n, ldx, mean, (double *)Xst, KT, KTP, nst);
+        else
+            hipLaunchKernelGGL((stage_kernel<double, float, true>), dim3(grid), dim3(256), 0, s, (const double *)X, t,
+                               n, ldx, mean, (float *)Xst, KT, KTP, nst);
+    } else {
+        if (prec == P_F64)
+            hipLaunchKernelGGL((stage_kernel<double, double, false>), dim3(grid), dim3(256), 0, s, (const double *)X,
+                               t, n, ldx, nullptr, (double *)Xst, KT, KTP, nst);
+        else if (in_f64)
+            hipLaunchKernelGGL((stage_kernel<double, float, false>), dim3(grid), dim3(256), 0, s, (const double *)X,
+                               t, n, ldx, nullptr, (float *)Xst, KT, KTP, nst);
+        else
+            hipLaunchKernelGGL((stage_kernel<float, float, false>), dim3(grid), dim3(256), 0, s, (const float *)X, t,
+                               n, ldx, nullptr, (float *)Xst, KT, KTP, nst);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Block moment contraction.
 //
 // A work item is one work-group tile (2 x 2 waves, each WM x WN blocks of
 // 32 x 32 entries) of one order's (prefix rows) x (suffix columns) product,
-// over one chunk of samples.  Samples are staged through LDS in stages of kt
-// samples (double-buffered, register prefetch, contiguous global reads of the
-// row-major data); every lane forms its Khatri-Rao operand values from the
-// staged samples: the product of the prefix (or suffix) variables of its row
-// (or column).  32 x 32 blocks with no stored entry (v > w everywhere) are
+// over one chunk of stages of one dataset.  Each stage is copied from HBM to
+// LDS by the DMA path (global_load_lds, 16 bytes per lane, no registers),
+// double-buffered.  Every lane forms its Khatri-Rao operand values from the
+// staged samples -- the product of the prefix (or suffix) variables of its
+// row (or column) -- reading VEC consecutive samples per variable with one
+// 16-byte LDS read.  The sample order inside a stage is a free choice of the
+// sum, so lane group g of an MFMA takes samples g*VEC .. g*VEC+VEC-1 of each
+// group of steps.  32 x 32 blocks with no stored entry (v > w everywhere) are
 // skipped per wave.  The chunk's sums go, in FP64, to the chunk's slice of
 // the partial buffer at each entry's block-storage offset.
 // ---------------------------------------------------------------------------
@@ -158,28 +238,39 @@ struct PT;
 template <>
 struct PT<P_F64> {
     typedef double T;
-    enum { KSTEP = 4, UMAX = 16, FLUSH = 0 };
+    enum { KT = 32, KTP = 36, FLUSH_STAGES = 0 };
 };
 template <>
 struct PT<P_F32> {
     typedef float T;
-    enum { KSTEP = 2, UMAX = 16, FLUSH = 64 };
+    enum { KT = 64, KTP = 68, FLUSH_STAGES = 1 };
 };
 template <>
 struct PT<P_BF16X2> {
     typedef float T;
-    enum { KSTEP = 16, UMAX = 16, FLUSH = 256 };
+    enum { KT = 64, KTP = 68, FLUSH_STAGES = 1 };
 };
 template <>
 struct PT<P_BF16X3> {
     typedef float T;
-    enum { KSTEP = 16, UMAX = 16, FLUSH = 256 };
+    enum { KT = 64, KTP = 68, FLUSH_STAGES = 1 };
 };
 
-int lds_bytes_moment(int prec, int n, int kt) {
-    if (prec >= P_BF16X2) return 2 * (n + 1) * (kt + 4) * 4;
-    return 2 * kt * (n + 1) * (prec == P_F64 ? 8 : 4);
+int lds_bytes_moment(int prec, int n) { return 2 * (n + 1) * stage_pitch(prec) * stage_esize(prec); }
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Copy one stage (bytes, a multiple of 16) from global to LDS with the DMA
+// path: each wave moves 1 KiB per instruction, lane l its 16-byte piece.
+__device__ __forceinline__ void stage_dma(const char *src, char *lds, int bytes, int wave, int lane) {
+    for (int c = wave * 1024; c < bytes; c += 4 * 1024) {
+        const int off = c + lane * 16;
+        if (off < bytes)
+            __builtin_amdgcn_global_load_lds((const void *)(src + off), (lds_void *)(lds + c), 16, 0, 0);
+    }
 }
+
+__device__ __forceinline__ void wait_dma() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
 __device__ __forceinline__ void split2(const float *v, bf8 &hi, bf8 &lo) {
 #pragma unroll
@@ -202,19 +293,20 @@ __device__ __forceinline__ void split3(const float *v, bf8 &hi, bf8 &mid, bf8 &l
     }
 }
 
+typedef double d2 __attribute__((ext_vector_type(2)));
+
 template <int PREC, int WM, int WN, int P, int Q>
-__device__ __forceinline__ void moment_item(const MomentArgs &a, const Item &item, const TileDev &tile,
-                                            const OrderDev &od, const SetDev &sd, typename PT<PREC>::T *xs,
-                                            const int *lpos, int wave) {
+__device__ __forceinline__ void moment_item(const Item &item, const TileDev &tile, const OrderDev &od,
+                                            const SetDev &sd, char *lds, int n, int wave) {
     typedef typename PT<PREC>::T T;
-    constexpr bool TRANS = PREC >= P_BF16X2;  // LDS as [variable][sample]
-    constexpr int RH = (PREC == P_F64) ? 2 : 1; // operand rows per lane per 32-block
-    constexpr int UMAX = PT<PREC>::UMAX;
-    const int n = a.n, kt = a.kt, tid = threadIdx.x, lane = tid & 63;
+    constexpr int KT = PT<PREC>::KT, KTP = PT<PREC>::KTP;
+    constexpr int RH = (PREC == P_F64) ? 2 : 1;  // operand rows per lane per 32-block
+    const int tid = threadIdx.x, lane = tid & 63;
     const int wy = wave >> 1, wx = wave & 1;
-    const int ld = n + 1, ldt = kt + 4;
-    const int buf_elems = TRANS ? (n + 1) * ldt : kt * ld;
+    const int stage_bytes = (n + 1) * KTP * (int)sizeof(T);
     const int rbase = tile.row0 + wy * (WM * 32), cbase = tile.col0 + wx * (WN * 32);
+    // first sample of this lane's group inside a step group
+    const int soff = (PREC == P_F64) ? 2 * (lane >> 4) : (PREC == P_F32 ? 4 * (lane >> 5) : 8 * (lane >> 5));
 
     // which of this wave's 32 x 32 blocks hold stored entries (wave-uniform)
     unsigned vmask = 0;
@@ -226,7 +318,7 @@ __device__ __forceinline__ void moment_item(const MomentArgs &a, const Item &ite
             if (r0 < od.nr && c0 < od.nc && od.rb_vmin[r0 >> 5] <= od.cb_wmax[c0 >> 5]) vmask |= 1u << (i * WN + j);
         }
 
-    // operand offsets into LDS of this lane's rows and columns
+    // LDS offsets (in T) of this lane's operand variables, plus its sample offset
     int roff[WM][RH][P], coff[WN][RH][Q];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
@@ -239,7 +331,7 @@ __device__ __forceinline__ void moment_item(const MomentArgs &a, const Item &ite
             else
                 for (int q = 0; q < MAXH; ++q) f.var[q] = (uint8_t)n;
 #pragma unroll
-            for (int q = 0; q < P; ++q) roff[i][h][q] = TRANS ? f.var[q] * ldt : f.var[q];
+            for (int q = 0; q < P; ++q) roff[i][h][q] = f.var[q] * KTP + soff;
         }
 #pragma unroll
     for (int j = 0; j < WN; ++j)
@@ -252,10 +344,9 @@ __device__ __forceinline__ void moment_item(const MomentArgs &a, const Item &ite
             else
                 for (int q = 0; q < MAXH; ++q) f.var[q] = (uint8_t)n;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) coff[j][h][q] = TRANS ? f.var[q] * ldt : f.var[q];
+            for (int q = 0; q < Q; ++q) coff[j][h][q] = f.var[q] * KTP + soff;
         }
 
-    // accumulators
     d4 acc64[WM][WN][RH][RH];
     f16v acc[WM][WN];
     double dacc[WM][WN][16];
@@ -272,118 +363,100 @@ __device__ __forceinline__ void moment_item(const MomentArgs &a, const Item &ite
 #pragma unroll
         for (int i = 0; i < WM; ++i)
 #pragma unroll
-            for (int j = 0; j < WN; ++j) {
+            for (int j = 0; j < WN; ++j)
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     acc[i][j][k] = 0.f;
                     dacc[i][j][k] = 0.0;
                 }
-            }
     }
 
-    const int64_t s0 = (int64_t)item.chunk * sd.chunk_len;
-    const int64_t s1 = min(sd.t, s0 + sd.chunk_len);
-    const int nk = (int)((s1 - s0 + kt - 1) / kt);
-    const T *X = reinterpret_cast<const T *>(sd.X);
-
-    T pf[UMAX];
-    auto gload = [&](int k) {
-        const int64_t sb = s0 + (int64_t)k * kt;
-        const T *src = X + sb * n;
-        const int64_t left = s1 - sb;
-#pragma unroll
-        for (int u = 0; u < UMAX; ++u) {
-            pf[u] = T(0);
-            if (lpos[u] >= 0 && (lpos[u] >> 20) < left) pf[u] = src[tid + 256 * u];
-        }
-    };
-    auto lstore = [&](int buf) {
-        T *dst = xs + buf * buf_elems;
-#pragma unroll
-        for (int u = 0; u < UMAX; ++u)
-            if (lpos[u] >= 0) dst[lpos[u] & 0xFFFFF] = pf[u];
-    };
+    const int64_t st0 = (int64_t)item.chunk * sd.chunk_stages;
+    const int nst = (int)(min(sd.nstages, st0 + sd.chunk_stages) - st0);
+    const char *src = reinterpret_cast<const char *>(sd.X) + st0 * (int64_t)stage_bytes;
 
     __syncthreads();  // the previous item's readers are done with both buffers
-    gload(0);
-    lstore(0);
+    stage_dma(src, lds, stage_bytes, wave, lane);
+    wait_dma();
     __syncthreads();
 
-    const int flush_every = (PT<PREC>::FLUSH > 0) ? max(1, (int)PT<PREC>::FLUSH / kt) : 0;
     int since_flush = 0;
-
-    for (int k = 0; k < nk; ++k) {
-        const int buf = k & 1;
-        if (k + 1 < nk) gload(k + 1);
-        const T *xb = xs + buf * buf_elems;
+    for (int k = 0; k < nst; ++k) {
+        const T *xb = reinterpret_cast<const T *>(lds + (k & 1) * stage_bytes);
+        if (k + 1 < nst) stage_dma(src + (int64_t)(k + 1) * stage_bytes, lds + ((k + 1) & 1) * stage_bytes, stage_bytes, wave, lane);
         if (vmask) {
             if constexpr (PREC == P_F64) {
-                for (int kk = 0; kk < kt; kk += 4) {
-                    const double *xr = xb + (kk + (lane >> 4)) * ld;
-                    double A[WM][2], B[WN][2];
+#pragma unroll
+                for (int kk = 0; kk < KT; kk += 8) {
+                    d2 A[WM][2], B[WN][2];
 #pragma unroll
                     for (int i = 0; i < WM; ++i)
 #pragma unroll
                         for (int h = 0; h < 2; ++h) {
-                            double v = xr[roff[i][h][0]];
+                            d2 v = *reinterpret_cast<const d2 *>(xb + roff[i][h][0] + kk);
 #pragma unroll
-                            for (int q = 1; q < P; ++q) v *= xr[roff[i][h][q]];
+                            for (int q = 1; q < P; ++q) v *= *reinterpret_cast<const d2 *>(xb + roff[i][h][q] + kk);
                             A[i][h] = v;
                         }
 #pragma unroll
                     for (int j = 0; j < WN; ++j)
 #pragma unroll
                         for (int h = 0; h < 2; ++h) {
-                            double v = xr[coff[j][h][0]];
+                            d2 v = *reinterpret_cast<const d2 *>(xb + coff[j][h][0] + kk);
 #pragma unroll
-                            for (int q = 1; q < Q; ++q) v *= xr[coff[j][h][q]];
+                            for (int q = 1; q < Q; ++q) v *= *reinterpret_cast<const d2 *>(xb + coff[j][h][q] + kk);
                             B[j][h] = v;
                         }
 #pragma unroll
-                    for (int i = 0; i < WM; ++i)
+                    for (int u = 0; u < 2; ++u)
 #pragma unroll
-                        for (int j = 0; j < WN; ++j)
-                            if (vmask >> (i * WN + j) & 1u) {
+                        for (int i = 0; i < WM; ++i)
 #pragma unroll
-                                for (int h = 0; h < 2; ++h)
+                            for (int j = 0; j < WN; ++j)
+                                if (vmask >> (i * WN + j) & 1u) {
 #pragma unroll
-                                    for (int g = 0; g < 2; ++g)
-                                        acc64[i][j][h][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                            A[i][h], B[j][g], acc64[i][j][h][g], 0, 0, 0);
-                            }
+                                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                                        for (int g = 0; g < 2; ++g)
+                                            acc64[i][j][h][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                                A[i][h][u], B[j][g][u], acc64[i][j][h][g], 0, 0, 0);
+                                }
                 }
             } else if constexpr (PREC == P_F32) {
-                for (int kk = 0; kk < kt; kk += 2) {
-                    const float *xr = xb + (kk + (lane >> 5)) * ld;
-                    float A[WM], B[WN];
+#pragma unroll
+                for (int kk = 0; kk < KT; kk += 8) {
+                    f4 A[WM], B[WN];
 #pragma unroll
                     for (int i = 0; i < WM; ++i) {
-                        float v = xr[roff[i][0][0]];
+                        f4 v = *reinterpret_cast<const f4 *>(xb + roff[i][0][0] + kk);
 #pragma unroll
-                        for (int q = 1; q < P; ++q) v *= xr[roff[i][0][q]];
+                        for (int q = 1; q < P; ++q) v *= *reinterpret_cast<const f4 *>(xb + roff[i][0][q] + kk);
                         A[i] = v;
                     }
 #pragma unroll
                     for (int j = 0; j < WN; ++j) {
-                        float v = xr[coff[j][0][0]];
+                        f4 v = *reinterpret_cast<const f4 *>(xb + coff[j][0][0] + kk);
 #pragma unroll
-                        for (int q = 1; q < Q; ++q) v *= xr[coff[j][0][q]];
+                        for (int q = 1; q < Q; ++q) v *= *reinterpret_cast<const f4 *>(xb + coff[j][0][q] + kk);
                         B[j] = v;
                     }
 #pragma unroll
-                    for (int i = 0; i < WM; ++i)
+                    for (int u = 0; u < 4; ++u)
 #pragma unroll
-                        for (int j = 0; j < WN; ++j)
-                            if (vmask >> (i * WN + j) & 1u)
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i], B[j], acc[i][j], 0, 0, 0);
+                        for (int i = 0; i < WM; ++i)
+#pragma unroll
+                            for (int j = 0; j < WN; ++j)
+                                if (vmask >> (i * WN + j) & 1u)
+                                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i][u], B[j][u], acc[i][j], 0, 0, 0);
                 }
             } else {
-                for (int kk = 0; kk < kt; kk += 16) {
-                    const float *xr = xb + kk + 8 * (lane >> 5);
-                    constexpr int NS = (PREC == P_BF16X3) ? 3 : 2;
+                constexpr int NS = (PREC == P_BF16X3) ? 3 : 2;
+#pragma unroll 2
+                for (int kk = 0; kk < KT; kk += 16) {
                     bf8 As[WM][NS], Bs[WN][NS];
 #pragma unroll
                     for (int i = 0; i < WM; ++i) {
+                        const T *xr = xb + kk;
                         f4 v0 = *reinterpret_cast<const f4 *>(xr + roff[i][0][0]);
                         f4 v1 = *reinterpret_cast<const f4 *>(xr + roff[i][0][0] + 4);
 #pragma unroll
@@ -399,6 +472,7 @@ __device__ __forceinline__ void moment_item(const MomentArgs &a, const Item &ite
                     }
 #pragma unroll
                     for (int j = 0; j < WN; ++j) {
+                        const T *xr = xb + kk;
                         f4 v0 = *reinterpret_cast<const f4 *>(xr + coff[j][0][0]);
                         f4 v1 = *reinterpret_cast<const f4 *>(xr + coff[j][0][0] + 4);
 #pragma unroll
@@ -413,11 +487,12 @@ __device__ __forceinline__ void moment_item(const MomentArgs &a, const Item &ite
                             split2(v, Bs[j][0], Bs[j][1]);
                     }
                     // cross products of the split terms: all 4 for two terms; for three
-                    // terms the 6 of combined weight >= 2^-16 (hh, hm, mh, hl, lh, mm)
+                    // terms the 6 of combined weight >= 2^-16 (hh, hm, mh, hl, lh, mm);
+                    // smallest first
                     constexpr int NP = (NS == 3) ? 6 : 4;
-                    constexpr int PA[4] = {0, 0, 1, 1};          // hh, hl, lh, ll
+                    constexpr int PA[4] = {0, 0, 1, 1};        // hh, hl, lh, ll
                     constexpr int PB[4] = {0, 1, 0, 1};
-                    constexpr int PA3[6] = {0, 0, 1, 0, 2, 1};    // hh, hm, mh, hl, lh, mm
+                    constexpr int PA3[6] = {0, 0, 1, 0, 2, 1};  // hh, hm, mh, hl, lh, mm
                     constexpr int PB3[6] = {0, 1, 0, 2, 0, 1};
 #pragma unroll
                     for (int pr = NP - 1; pr >= 0; --pr) {
@@ -435,10 +510,10 @@ __device__ __forceinline__ void moment_item(const MomentArgs &a, const Item &ite
                 }
             }
         }
-        if (k + 1 < nk) lstore(buf ^ 1);
+        wait_dma();
         __syncthreads();
         if constexpr (PREC != P_F64) {
-            if (++since_flush >= flush_every || k + 1 == nk) {
+            if (++since_flush >= PT<PREC>::FLUSH_STAGES || k + 1 == nst) {
                 since_flush = 0;
 #pragma unroll
                 for (int i = 0; i < WM; ++i)
@@ -496,36 +571,8 @@ __device__ __forceinline__ void moment_item(const MomentArgs &a, const Item &ite
 
 template <int PREC, int WM, int WN>
 __global__ __launch_bounds__(256, 2) void moment_kernel(MomentArgs a) {
-    typedef typename PT<PREC>::T T;
-    constexpr bool TRANS = PREC >= P_BF16X2;
-    constexpr int UMAX = PT<PREC>::UMAX;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *xs = reinterpret_cast<T *>(smem_raw);
-    const int n = a.n, kt = a.kt, tid = threadIdx.x;
-    const int ld = n + 1, ldt = kt + 4;
-    const int buf_elems = TRANS ? (n + 1) * ldt : kt * ld;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-
-    // the zero column (row, transposed) of both stages is never overwritten
-    if (TRANS) {
-        for (int i = tid; i < 2 * ldt; i += 256) xs[(i / ldt) * buf_elems + n * ldt + (i % ldt)] = T(0);
-    } else {
-        for (int i = tid; i < 2 * kt; i += 256) xs[(i / kt) * buf_elems + (i % kt) * ld + n] = T(0);
-    }
-    // this thread's share of one LDS stage: (sample row << 20) | LDS offset
-    int lpos[UMAX];
-    const int tile_elems = kt * n;
-#pragma unroll
-    for (int u = 0; u < UMAX; ++u) {
-        const int e = tid + 256 * u;
-        if (e < tile_elems) {
-            const int row = e / n, col = e - (e / n) * n;
-            lpos[u] = (row << 20) | (TRANS ? col * ldt + row : row * ld + col);
-        } else {
-            lpos[u] = -1;
-        }
-    }
-
+    extern __shared__ __align__(16) char lds[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
         const Item item = a.items[it];
         if (item.tile < 0) continue;
@@ -533,13 +580,13 @@ __global__ __launch_bounds__(256, 2) void moment_kernel(MomentArgs a) {
         const OrderDev od = a.ords[tile.ord];
         const SetDev sd = a.sets ? a.sets[item.set] : a.set0;
         switch (od.p * 8 + od.q) {
-            case 1 * 8 + 1: moment_item<PREC, WM, WN, 1, 1>(a, item, tile, od, sd, xs, lpos, wave); break;
-            case 1 * 8 + 2: moment_item<PREC, WM, WN, 1, 2>(a, item, tile, od, sd, xs, lpos, wave); break;
-            case 2 * 8 + 2: moment_item<PREC, WM, WN, 2, 2>(a, item, tile, od, sd, xs, lpos, wave); break;
-            case 2 * 8 + 3: moment_item<PREC, WM, WN, 2, 3>(a, item, tile, od, sd, xs, lpos, wave); break;
-            case 3 * 8 + 3: moment_item<PREC, WM, WN, 3, 3>(a, item, tile, od, sd, xs, lpos, wave); break;
-            case 3 * 8 + 4: moment_item<PREC, WM, WN, 3, 4>(a, item, tile, od, sd, xs, lpos, wave); break;
-            case 4 * 8 + 4: moment_item<PREC, WM, WN, 4, 4>(a, item, tile, od, sd, xs, lpos, wave); break;
+            case 1 * 8 + 1: moment_item<PREC, WM, WN, 1, 1>(item, tile, od, sd, lds, a.n, wave); break;
+            case 1 * 8 + 2: moment_item<PREC, WM, WN, 1, 2>(item, tile, od, sd, lds, a.n, wave); break;
+            case 2 * 8 + 2: moment_item<PREC, WM, WN, 2, 2>(item, tile, od, sd, lds, a.n, wave); break;
+            case 2 * 8 + 3: moment_item<PREC, WM, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave); break;
+            case 3 * 8 + 3: moment_item<PREC, WM, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave); break;
+            case 3 * 8 + 4: moment_item<PREC, WM, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave); break;
+            case 4 * 8 + 4: moment_item<PREC, WM, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave); break;
             default: break;
         }
     }
@@ -547,13 +594,16 @@ __global__ __launch_bounds__(256, 2) void moment_kernel(MomentArgs a) {
 
 template <int PREC>
 static hipError_t launch_moment_prec(int shape, const MomentArgs &a, int grid, hipStream_t s) {
-    const int lds = lds_bytes_moment(PREC, a.n, a.kt);
+    const int lds = lds_bytes_moment(PREC, a.n);
     switch (shape) {
         case TS_1x1:
             hipLaunchKernelGGL((moment_kernel<PREC, 1, 1>), dim3(grid), dim3(256), lds, s, a);
             break;
         case TS_2x1:
             hipLaunchKernelGGL((moment_kernel<PREC, 2, 1>), dim3(grid), dim3(256), lds, s, a);
+            break;
+        case TS_2x2:
+            hipLaunchKernelGGL((moment_kernel<PREC, 2, 2>), dim3(grid), dim3(256), lds, s, a);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -707,7 +757,7 @@ hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t
 }
 
 hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s) {
-    hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, s, part, groups, n, t, mean);
+    hipLaunchKernelGGL(mean_kernel, dim3(n), dim3(256), 0, s, part, groups, n, t, mean);
     return hipGetLastError();
 }
 
@@ -730,7 +780,7 @@ hipError_t launch_batch_colsum(const CenterSet *sets, int nsets, int max_groups,
 }
 
 hipError_t launch_batch_mean(const CenterSet *sets, int nsets, int n, hipStream_t s) {
-    hipLaunchKernelGGL(batch_mean_kernel, dim3(nsets), dim3(256), 0, s, sets, n);
+    hipLaunchKernelGGL(batch_mean_kernel, dim3(n, nsets), dim3(256), 0, s, sets, n);
     return hipGetLastError();
 }
 

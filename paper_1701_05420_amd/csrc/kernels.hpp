@@ -16,8 +16,8 @@ struct MomentArgs {
     int64_t nitems;
     const SetDev *sets;  // per-dataset records, or null: every item uses set0
     SetDev set0;
-    int32_t n;   // variables; LDS column / row n holds zeros
-    int32_t kt;  // samples per LDS stage, a multiple of 16
+    int32_t n;           // variables; staged row n holds zeros
+    int32_t pad;
 };
 
 struct RedArgs {
@@ -31,9 +31,12 @@ struct RedArgs {
 };
 
 // Work-group tile shapes: WM x WN blocks of 32 x 32 per wave, 2 x 2 waves.
-enum TileShape { TS_1x1 = 0, TS_2x1 = 2 };
+enum TileShape { TS_1x1 = 0, TS_2x2 = 1, TS_2x1 = 2 };
 
-int lds_bytes_moment(int prec, int n, int kt);
+int lds_bytes_moment(int prec, int n);
+// row-major data (FP64 with ldx, or FP32 with ldx) -> staged layout, optionally centred
+hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xst, int prec,
+                        bool center, bool in_f64, hipStream_t s);
 hipError_t launch_moment(int prec, int shape, const MomentArgs &a, int grid, hipStream_t s);
 hipError_t launch_reduce(const RedArgs &a, int nsets, hipStream_t s);
 hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,

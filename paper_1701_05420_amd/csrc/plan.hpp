@@ -22,7 +22,7 @@ namespace cum {
 
 constexpr int MAXD = 8;   // largest order
 constexpr int MAXH = 4;   // longest prefix / suffix = ceil(MAXD / 2)
-constexpr int MAXN = 255; // variables (index n is the zero column)
+constexpr int MAXN = 112; // variables (index n is the zero row of the staged data)
 constexpr int FEAT_BLOCK = 32;
 
 // One row (prefix) or column (suffix) of an order's contraction.
@@ -63,14 +63,24 @@ struct Item {
     int32_t pad;
 };
 
-// Per dataset: the (device-precision) centred data and its partial sums.
+// Staged layout of the centred data, as the contraction reads it.  Samples
+// are cut into stages of KT; stage s holds, for every variable v = 0..n
+// (v = n is an all-zero row used by padding positions), the KT samples
+// s*KT .. s*KT+KT-1 contiguously, followed by KTP - KT zeros:
+//   Xst[(s * (n + 1) + v) * KTP + k],
+// samples beyond t are zero.  One stage is one contiguous block of memory.
+constexpr int stage_kt(int prec) { return prec == 0 ? 32 : 64; }
+constexpr int stage_pitch(int prec) { return prec == 0 ? 36 : 68; }
+constexpr int stage_esize(int prec) { return prec == 0 ? 8 : 4; }
+
+// Per dataset: the staged centred data and its partial sums.
 struct SetDev {
-    const void *X;       // t x n, leading dimension n
-    int64_t t;
-    int64_t chunk_len;
+    const void *X;         // staged layout
+    int64_t nstages;       // ceil(t / KT)
+    int64_t chunk_stages;  // stages per sample chunk
     int64_t nchunks;
-    double *partial;     // nchunks x stride
-    int64_t stride;      // stored entries of all orders 2..d_max
+    double *partial;       // nchunks x stride
+    int64_t stride;        // stored entries of all orders 2..d_max
 };
 
 // Reduction / recursion records.

@@ -191,3 +191,31 @@ def test_center_entry_point(dev, orc):
         want = oXc if prec == "f64" else oXc.astype(np.float32).astype(np.float64)
         tol = 1e-13 if prec == "f64" else 1.2e-7
         assert np.abs(got - want).max() <= tol * np.abs(oXc).max()
+
+
+def test_autotune_and_tuned_configs(dev, orc):
+    """Every tile shape / chunking the autotuner may pick gives the oracle's
+    result to the path's tolerance, deterministically."""
+    torch, pc = dev
+    X = workloads.t_gamma_mix(t=30_000, n=24, seed=9)
+    Xd = torch.from_numpy(X).cuda()
+    _, Xc = orc.center(X)
+    offs_idx = {d: stored_sample(orc, 24, d, 4, 200, seed=d) for d in range(2, 6)}
+    want = {d: orc.cumulant_at(Xc, offs_idx[d][1]) for d in offs_idx}
+    for prec in PRECS:
+        for shape in ["64x64", "128x64", "128x128"]:
+            for target in [256, 1024, 4096]:
+                say(f"tuned prec={prec} shape={shape} target={target}")
+                pc.set_tuning(30_000, 24, 5, 4, prec, shape, target)
+                _, K1 = pc.cumulants(Xd, 5, 4, prec)
+                _, K2 = pc.cumulants(Xd, 5, 4, prec)
+                for d in range(2, 6):
+                    g = K1[d].cpu().numpy()
+                    assert np.array_equal(g, K2[d].cpu().numpy())
+                    e = rel(g[offs_idx[d][0]], want[d])
+                    assert e <= TOL[prec], (prec, shape, target, d, e)
+        pc.set_tuning(30_000, 24, 5, 4, prec, None)
+        best = pc.autotune(Xd, 5, 4, prec)
+        say(f"autotune {prec}: {best}")
+        assert best["shape"] in (0, 1, 2) and best["ms"] > 0
+        pc.set_tuning(30_000, 24, 5, 4, prec, None)
