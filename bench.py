@@ -108,6 +108,59 @@ def cpu_baseline(orc, X, n, d_max, b, pc, target_s):
             "seconds": dt}
 
 
+def bench_batched(torch, pc, prec, steps, warmup, tune):
+    """The 512-dataset workload: one graph replay per step vs one
+    cum_cumulants call per dataset; datasets/s and per-dataset latency."""
+    import workloads
+
+    name = "batch512-t-corr-n32"
+    w = workloads.WORKLOADS[name]
+    n, b, d_max = w["n"], w["b"], w["d_max"]
+    Xs = workloads.generate(name)
+    ts = [len(X) for X in Xs]
+    Xd = [torch.from_numpy(X).cuda() for X in Xs]
+    flops = sum(alg_flops(pc, t, n, d_max, b) for t in ts)
+    batch = pc.Batch(ts, n, d_max, b, prec)
+    tuned = batch.autotune(Xd) if tune else None
+    out = [{d: torch.empty(pc.layout(n, d, b)["elems"], dtype=torch.float64, device="cuda")
+            for d in range(2, d_max + 1)} for _ in ts]
+    means = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in ts]
+    for _ in range(warmup):
+        batch.run(Xd, out=out, means=means)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.run(Xd, out=out, means=means)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    start, ticks, hz = batch.timestamps()
+    lat = np.array([(tk - start) / hz * 1e3 for tk in ticks])
+    batch.close()
+    # one launch sequence per dataset, same precision, buffers preallocated
+    wsz = max(pc.workspace_size(t, n, d_max, b, prec) for t in ts)
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    for s in range(min(8, len(ts))):
+        pc.cumulants(Xd[s], d_max, b, prec, ws=ws, out=out[s])
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in ts]
+    t0 = time.perf_counter()
+    ev0.record()
+    for s in range(len(ts)):
+        pc.cumulants(Xd[s], d_max, b, prec, ws=ws, out=out[s])
+        evs[s].record()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    seq_lat = np.array([ev0.elapsed_time(e) for e in evs])
+    return {"workload": name, "n_sets": len(ts), "prec": prec, "t_total": int(sum(ts)),
+            "ms_per_batch": ms, "datasets_per_s": len(ts) / ms * 1e3, "eff_tflops": flops / (ms * 1e-3) / 1e12,
+            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+            "per_dataset_calls": {"ms_total": seq_ms, "datasets_per_s": len(ts) / seq_ms * 1e3,
+                                  "latency_ms_p50": float(np.percentile(seq_lat, 50)),
+                                  "latency_ms_p99": float(np.percentile(seq_lat, 99))},
+            "tuning": tuned}
+
+
 def traffic_record(prec, workload):
     """HBM bytes per moment launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
@@ -134,6 +187,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (planner defaults)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-dataset batched measurement")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -206,6 +260,11 @@ def main():
         "paths": {p: {k: v for k, v in res[p].items()} for p in precs},
         "rel_err": {str(d): errs[d] for d in errs},
     }
+    if not args.no_batched:
+        log("batched workload")
+        line["batched"] = bench_batched(torch, pc, main_p, max(3, args.steps // 4), 1, not args.no_tune)
+        log(f"  batched: {line['batched']['datasets_per_s']:.0f} datasets/s vs "
+            f"{line['batched']['per_dataset_calls']['datasets_per_s']:.0f} with one call per dataset")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(orc, X, n, d_max, b, pc, args.cpu_seconds)

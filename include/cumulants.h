@@ -146,44 +146,6 @@ cum_status cum_unfold(const double *blocks, int n, int d, int b, double *dense, 
 cum_status cum_stored_offset(int n, int d, int b, const int32_t *idx /* host */, int64_t *offset /* host */);
 
 /* ------------------------------------------------------------------------
- * Batched cumulants: many datasets of the same width n and uneven sample
- * counts, computed by one persistent launch of the moment contraction over
- * all (dataset, tile, sample-chunk) work items, between one batched centring
- * launch and one batched reduction/recursion launch per pair of orders, all
- * captured once in a HIP graph and replayed.  Each dataset's result is
- * bitwise the one cum_cumulants() gives for it with the same prec.
- * ------------------------------------------------------------------------ */
-typedef struct cum_batch cum_batch;
-
-/* Host only (allocates the plan's device memory).  t_i (host, n_sets
- * entries, each >= 1). */
-cum_status cum_batch_create(int n_sets, const int64_t *t_i /* host */, int n, int d_max, int b, cum_prec prec,
-                            cum_batch **plan /* host out */);
-
-/*   X_i    (host) n_sets device pointers, dataset s is t_i[s] x n FP64, ld n
- *   kappa  (host) n_sets*(d_max-1) device pointers: kappa[s*(d_max-1)+d-2]
- *          receives c_d of dataset s in block storage
- *   mean   (host) n_sets device pointers (n FP64 each) or NULL
- * The first call captures the graph on stream; later calls copy the pointer
- * tables and replay it. */
-cum_status cum_batch_run(cum_batch *plan, const double *const *X_i, double *const *kappa, double *const *mean,
-                         void *stream);
-
-/* Host only.  After a cum_batch_run has completed: per-dataset device
- * timestamps (ticks of the 100 MHz constant clock), written when the
- * dataset's last order was finalised, and the start timestamp of the run.
- * ticks: n_sets entries.  Frequency in Hz goes to *hz. */
-cum_status cum_batch_timestamps(cum_batch *plan, uint64_t *start /* host */, uint64_t *ticks /* host */,
-                                double *hz /* host */);
-
-cum_status cum_batch_destroy(cum_batch *plan);
-
-/* Host only.  Check that the moment-contraction tiling of order d covers
- * every stored entry exactly once (no GPU needed).  Returns CUM_OK or
- * CUM_EINVAL with a message. */
-cum_status cum_plan_check(int n, int d, int b);
-
-/* ------------------------------------------------------------------------
  * Autotuning of the contraction's launch shape (the paper picks its block
  * size b by timing, Section 5.2; here b is the caller's storage choice and
  * the tuned knobs are the launch's):
@@ -214,6 +176,52 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
 /* Host only.  Set (tune != NULL) or forget (tune == NULL) the configuration
  * used for cum_cumulants(t, n, d_max, b, prec). */
 cum_status cum_set_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, const cum_tuning *tune /* host */);
+
+/* ------------------------------------------------------------------------
+ * Batched cumulants: many datasets of the same width n and uneven sample
+ * counts, computed by one persistent launch of the moment contraction over
+ * all (dataset, tile, sample-chunk) work items, between one batched centring
+ * launch and one batched reduction/recursion launch per pair of orders, all
+ * captured once in a HIP graph and replayed.  Results are deterministic
+ * (the same plan gives bitwise the same output on every run) and carry the
+ * accuracy of cum_cumulants() for the same prec.
+ * ------------------------------------------------------------------------ */
+typedef struct cum_batch cum_batch;
+
+/* Host only (allocates the plan's device memory).  t_i (host, n_sets
+ * entries, each >= 1). */
+cum_status cum_batch_create(int n_sets, const int64_t *t_i /* host */, int n, int d_max, int b, cum_prec prec,
+                            cum_batch **plan /* host out */);
+
+/*   X_i    (host) n_sets device pointers, dataset s is t_i[s] x n FP64, ld n
+ *   kappa  (host) n_sets*(d_max-1) device pointers: kappa[s*(d_max-1)+d-2]
+ *          receives c_d of dataset s in block storage
+ *   mean   (host) n_sets device pointers (n FP64 each) or NULL
+ * The first call captures the graph on stream; later calls copy the pointer
+ * tables and replay it. */
+cum_status cum_batch_run(cum_batch *plan, const double *const *X_i, double *const *kappa, double *const *mean,
+                         void *stream);
+
+/* Host only.  After a cum_batch_run has completed: per-dataset device
+ * timestamps (ticks of the 100 MHz constant clock), written when the
+ * dataset's last order was finalised, and the start timestamp of the run.
+ * ticks: n_sets entries.  Frequency in Hz goes to *hz. */
+cum_status cum_batch_timestamps(cum_batch *plan, uint64_t *start /* host */, uint64_t *ticks /* host */,
+                                double *hz /* host */);
+
+/* Time the batch's candidate launch configurations (tile shape x work-item
+ * target) on the datasets X_i (host array of device pointers) and keep the
+ * fastest for this plan (and for later plans of the same shape and count);
+ * the graph is captured again on the next run.  Synchronises the device.
+ * best (host) may be NULL. */
+cum_status cum_batch_autotune(cum_batch *plan, const double *const *X_i, cum_tuning *best /* host */);
+
+cum_status cum_batch_destroy(cum_batch *plan);
+
+/* Host only.  Check that the moment-contraction tiling of order d covers
+ * every stored entry exactly once (no GPU needed).  Returns CUM_OK or
+ * CUM_EINVAL with a message. */
+cum_status cum_plan_check(int n, int d, int b);
 
 /* Host only.  Measurement helpers.  While enabled on the calling thread,
  * every kernel launch made by the entry points on that thread is bracketed by

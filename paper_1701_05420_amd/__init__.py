@@ -31,8 +31,8 @@ MAX_ORDER = 8
 EXPORTS = [
     "cum_layout_query", "cum_workspace_size", "cum_center", "cum_moment_blocks", "cum_cumulants", "cum_unfold",
     "cum_stored_offset", "cum_batch_create", "cum_batch_run", "cum_batch_timestamps", "cum_batch_destroy",
-    "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning", "cum_status_str",
-    "cum_last_error",
+    "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning",
+    "cum_batch_autotune", "cum_status_str", "cum_last_error",
 ]
 SHAPES = {"64x64": 0, "128x128": 1, "128x64": 2}
 
@@ -65,6 +65,7 @@ _lib.cum_plan_check.argtypes = [_I, _I, _I]
 _lib.cum_timing_enable.argtypes = [_I]
 _lib.cum_autotune.argtypes = [_VP, _I64, _I, _I64, _I, _I, _I, _VP, ctypes.POINTER(Tuning)]
 _lib.cum_set_tuning.argtypes = [_I64, _I, _I, _I, _I, ctypes.POINTER(Tuning)]
+_lib.cum_batch_autotune.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(Tuning)]
 _lib.cum_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]
 _lib.cum_status_str.argtypes = [_I]
 _lib.cum_status_str.restype = ctypes.c_char_p
@@ -273,6 +274,13 @@ class Batch:
         _check(_lib.cum_batch_run(self._h, xs, ks, ms, _stream(stream)))
         self._keep = (X_list, out, means)
         return means, out
+
+    def autotune(self, X_list):
+        """Time the launch configurations on these datasets; keep the fastest."""
+        xs = (_VP * len(X_list))(*[X.data_ptr() for X in X_list])
+        out = Tuning()
+        _check(_lib.cum_batch_autotune(self._h, xs, ctypes.byref(out)))
+        return {"shape": out.shape, "target_items": out.target_items, "ms": out.ms}
 
     def timestamps(self):
         ns = len(self.t)

@@ -957,19 +957,410 @@ cum_status cum_timing_read(double *ms, int64_t *launches) {
     return st;
 }
 
+// ---------------------------------------------------------------------------
+// Batched cumulants.
+// ---------------------------------------------------------------------------
 struct cum_batch {
-    int dummy;
+    int nsets = 0, n = 0, d_max = 0, b = 0, prec = 0, shape = 0;
+    int64_t chunk_stages = 0, stride = 0, nitems = 0;
+    std::vector<int64_t> t;
+    std::vector<OrderPlan *> orders;  // d = 2..d_max
+    std::vector<int64_t> out_off;
+    std::vector<OrderDev> ods;
+    std::vector<RedOrder> red;
+    std::vector<HostTile> tiles;
+    std::vector<SetDev> sets;
+    std::vector<SetRed> setred;
+    std::vector<CenterSet> csets;
+    int max_groups = 1, stage_blocks = 1;
+    DevBuf ords_d, tiles_d, items_d, red_d, sets_d, setred_d, cset_d;
+    DevBuf staged_d, partial_d, part_d, mean_d, stamps_d;
+    CenterSet *h_cset = nullptr;  // pinned staging of the per-run pointer tables
+    SetRed *h_setred = nullptr;
+    hipEvent_t copied = nullptr, done = nullptr, ready = nullptr;
+    hipStream_t stream = nullptr;     // the plan's own stream (graph capture and replay)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool pending_copy = false;
 };
 
-cum_status cum_batch_create(int, const int64_t *, int, int, int, cum_prec, cum_batch **) {
-    return fail(CUM_EUNSUPPORTED, "batched path not built yet");
+static void batch_free(cum_batch *p) {
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->h_cset) (void)hipHostFree(p->h_cset);
+    if (p->h_setred) (void)hipHostFree(p->h_setred);
+    if (p->copied) (void)hipEventDestroy(p->copied);
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->ready) (void)hipEventDestroy(p->ready);
+    if (p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
 }
-cum_status cum_batch_run(cum_batch *, const double *const *, double *const *, double *const *, void *) {
-    return fail(CUM_EUNSUPPORTED, "batched path not built yet");
+
+// Work items of a batch: datasets go to XCDs by longest-processing-time
+// first (so each dataset's staged data stays in one XCD's L2); on each XCD
+// the items run most expensive first; item i of the launch runs on XCD i % 8.
+static std::vector<Item> batch_items(const cum_batch &p) {
+    int64_t tile_cost = 0;
+    for (auto &h : p.tiles) tile_cost += h.cost;
+    std::vector<int> order(p.nsets);
+    for (int s = 0; s < p.nsets; ++s) order[s] = s;
+    std::vector<int64_t> nst(p.nsets);
+    for (int s = 0; s < p.nsets; ++s) nst[s] = p.sets[s].nstages;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nst[x] > nst[y]; });
+    int64_t load[8] = {0};
+    std::vector<std::vector<std::pair<int64_t, Item>>> per_xcd(8);
+    for (int s : order) {
+        int x = (int)(std::min_element(load, load + 8) - load);
+        load[x] += nst[s] * tile_cost;
+        for (int64_t ch = 0; ch < p.sets[s].nchunks; ++ch) {
+            const int64_t len = std::min(p.chunk_stages, nst[s] - ch * p.chunk_stages);
+            for (size_t ti = 0; ti < p.tiles.size(); ++ti)
+                per_xcd[x].push_back({len * p.tiles[ti].cost, Item{(int32_t)ti, (int32_t)ch, (int32_t)s, 0}});
+        }
+    }
+    size_t longest = 0;
+    for (auto &v : per_xcd) {
+        std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, Item> &a, const std::pair<int64_t, Item> &b) {
+            return a.first > b.first;
+        });
+        longest = std::max(longest, v.size());
+    }
+    std::vector<Item> items;
+    for (size_t i = 0; i < longest; ++i)
+        for (int x = 0; x < 8; ++x) items.push_back(i < per_xcd[x].size() ? per_xcd[x][i].second : Item{-1, 0, 0, 0});
+    while (!items.empty() && items.back().tile < 0) items.pop_back();
+    return items;
 }
-cum_status cum_batch_timestamps(cum_batch *, uint64_t *, uint64_t *, double *) {
-    return fail(CUM_EUNSUPPORTED, "batched path not built yet");
+
+// (Re)build the tiles, chunking and items for a shape and target, and the
+// per-dataset records that depend on them.
+static cum_status batch_layout(cum_batch &p, int shape, int target) {
+    int wm, wn;
+    shape_dims(shape, wm, wn);
+    p.shape = shape;
+    p.tiles.clear();
+    for (size_t i = 0; i < p.orders.size(); ++i) order_tiles(*p.orders[i], wm, wn, (int)i, p.tiles);
+    std::stable_sort(p.tiles.begin(), p.tiles.end(), [](const HostTile &x, const HostTile &y) { return x.cost > y.cost; });
+    const int KT = stage_kt(p.prec);
+    int64_t total_st = 0, max_st = 1;
+    for (int s = 0; s < p.nsets; ++s) {
+        const int64_t nst = (p.t[s] + KT - 1) / KT;
+        total_st += nst;
+        max_st = std::max(max_st, nst);
+    }
+    // chunk length: about `target` items overall, whole datasets when that is enough
+    const int64_t ntiles = (int64_t)p.tiles.size();
+    int64_t cs = std::max<int64_t>(4, (total_st * ntiles + target - 1) / std::max<int64_t>(target, 1));
+    p.chunk_stages = std::min(cs, max_st);
+    int64_t poff = 0;
+    for (int s = 0; s < p.nsets; ++s) {
+        SetDev &sd = p.sets[s];
+        sd.nstages = (p.t[s] + KT - 1) / KT;
+        sd.chunk_stages = p.chunk_stages;
+        sd.nchunks = (sd.nstages + p.chunk_stages - 1) / p.chunk_stages;
+        sd.stride = p.stride;
+        sd.partial = reinterpret_cast<double *>(poff);  // offset; rebased after allocation
+        poff += sd.nchunks * p.stride;
+    }
+    auto items = batch_items(p);
+    p.nitems = (int64_t)items.size();
+    cum_status st;
+    std::vector<TileDev> tdev;
+    for (auto &h : p.tiles) tdev.push_back(h.t);
+    if ((st = upload(p.tiles_d, tdev)) || (st = upload(p.items_d, items))) return st;
+    if (p.partial_d.p) {
+        (void)hipFree(p.partial_d.p);
+        p.partial_d.p = nullptr;
+    }
+    HIP_TRY(hipMalloc(&p.partial_d.p, std::max<int64_t>(1, poff) * sizeof(double)));
+    for (int s = 0; s < p.nsets; ++s) {
+        p.sets[s].partial = (double *)p.partial_d.p + (int64_t)(intptr_t)p.sets[s].partial;
+        p.setred[s].partial = p.sets[s].partial;
+        p.setred[s].nchunks = p.sets[s].nchunks;
+    }
+    if ((st = upload(p.sets_d, p.sets))) return st;
+    if (p.exec) {
+        (void)hipGraphExecDestroy(p.exec);
+        p.exec = nullptr;
+    }
+    if (p.graph) {
+        (void)hipGraphDestroy(p.graph);
+        p.graph = nullptr;
+    }
+    return CUM_OK;
 }
-cum_status cum_batch_destroy(cum_batch *) { return CUM_OK; }
+
+static cum_status batch_enqueue(cum_batch &p, hipStream_t s) {
+    HIP_TRY(launch_batch_stamp((unsigned long long *)p.stamps_d.p, p.nsets, s));
+    const CenterSet *cs = (const CenterSet *)p.cset_d.p;
+    HIP_TRY(launch_batch_colsum(cs, p.nsets, p.max_groups, p.n, s));
+    HIP_TRY(launch_batch_mean(cs, p.nsets, p.n, s));
+    HIP_TRY(launch_batch_stage(cs, p.nsets, p.n, p.prec, p.stage_blocks, s));
+    MomentArgs ma;
+    memset(&ma, 0, sizeof ma);
+    ma.ords = (const OrderDev *)p.ords_d.p;
+    ma.tiles = (const TileDev *)p.tiles_d.p;
+    ma.items = (const Item *)p.items_d.p;
+    ma.nitems = p.nitems;
+    ma.sets = (const SetDev *)p.sets_d.p;
+    ma.n = p.n;
+    if (p.nitems > 0) HIP_TRY(launch_moment(p.prec, p.shape, ma, (int)p.nitems, s));
+    const RedOrder *red_d = (const RedOrder *)p.red_d.p;
+    for (int d = 2; d <= p.d_max; d += 2) {
+        RedArgs ra;
+        memset(&ra, 0, sizeof ra);
+        const int i0 = d - 2;
+        ra.ords = red_d + i0;
+        ra.nords = (d + 1 <= p.d_max) ? 2 : 1;
+        ra.recursion = 1;
+        ra.nb0 = p.red[i0].nblocks;
+        ra.nbtot = ra.nb0 + (ra.nords == 2 ? p.red[i0 + 1].nblocks : 0);
+        ra.sets = (const SetRed *)p.setred_d.p;
+        HIP_TRY(launch_reduce(ra, p.nsets, s));
+    }
+    return CUM_OK;
+}
+
+cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, int b, cum_prec prec,
+                            cum_batch **plan) {
+    cum_status st;
+    if (!plan || !t_i) return fail(CUM_EINVAL, "NULL argument");
+    *plan = nullptr;
+    if (n_sets < 1 || n_sets > 65535) return fail(CUM_EINVAL, "n_sets must be in 1..65535");
+    if ((st = check_common(1, n, b)) || (st = check_prec(prec))) return st;
+    if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
+    for (int s = 0; s < n_sets; ++s)
+        if (t_i[s] < 1) return fail(CUM_EINVAL, "t_i[%d] = %lld < 1", s, (long long)t_i[s]);
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::unique_ptr<cum_batch, void (*)(cum_batch *)> p(new cum_batch, batch_free);
+    p->nsets = n_sets;
+    p->n = n;
+    p->d_max = d_max;
+    p->b = b;
+    p->prec = prec;
+    p->t.assign(t_i, t_i + n_sets);
+    int64_t off = 0;
+    for (int d = 2; d <= d_max; ++d) {
+        OrderPlan *o;
+        if ((st = get_order(n, b, d, &o)) || (st = upload_order(*o))) return st;
+        p->orders.push_back(o);
+        p->out_off.push_back(off);
+        OrderDev od;
+        od.rows = (const Feat *)o->rows_d.p;
+        od.cols = (const Feat *)o->cols_d.p;
+        od.rb_vmin = (const int32_t *)o->rbv_d.p;
+        od.cb_wmax = (const int32_t *)o->cbw_d.p;
+        od.H = (const int64_t *)o->H_d.p;
+        od.out_off = off;
+        od.elems = o->elems;
+        od.d = d;
+        od.p = o->p;
+        od.q = o->q;
+        od.nbar = o->nbar;
+        od.b = b;
+        od.nr = o->nr;
+        od.nc = o->nc;
+        od.pad = 0;
+        p->ods.push_back(od);
+        RedOrder ro;
+        ro.tuples = (const uint8_t *)o->tuples_d.p;
+        ro.parts = (const uint16_t *)o->parts_d.p;
+        ro.nblocks = o->nblocks;
+        ro.out_off = off;
+        ro.d = d;
+        ro.npart = o->npart;
+        ro.nbar = o->nbar;
+        ro.b = b;
+        p->red.push_back(ro);
+        off += o->elems;
+    }
+    p->stride = off;
+    if ((st = upload(p->ords_d, p->ods)) || (st = upload(p->red_d, p->red))) return st;
+    // per-dataset storage: staged data, centring partial sums, means scratch
+    const int KT = stage_kt(prec), KTP = stage_pitch(prec);
+    int64_t staged = 0, parts = 0;
+    p->sets.resize(n_sets);
+    p->setred.resize(n_sets);
+    p->csets.resize(n_sets);
+    std::vector<int64_t> st_off(n_sets), part_off(n_sets);
+    for (int s = 0; s < n_sets; ++s) {
+        int groups;
+        int64_t rows_per;
+        center_groups(p->t[s], groups, rows_per);
+        p->csets[s].groups = groups;
+        p->csets[s].rows_per = rows_per;
+        p->csets[s].t = p->t[s];
+        p->max_groups = std::max(p->max_groups, groups);
+        st_off[s] = staged;
+        staged += (p->t[s] + KT - 1) / KT * (int64_t)(n + 1) * KTP * stage_esize(prec);
+        staged = (int64_t)align_up((size_t)staged);
+        part_off[s] = parts;
+        parts += (int64_t)groups * n * 2;
+    }
+    HIP_TRY(hipMalloc(&p->staged_d.p, std::max<int64_t>(staged, 256)));
+    HIP_TRY(hipMalloc(&p->part_d.p, std::max<int64_t>(parts, 1) * sizeof(double)));
+    HIP_TRY(hipMalloc(&p->mean_d.p, (size_t)n_sets * n * sizeof(double)));
+    HIP_TRY(hipMalloc(&p->stamps_d.p, (size_t)(n_sets + 1) * sizeof(unsigned long long)));
+    for (int s = 0; s < n_sets; ++s) {
+        CenterSet &c = p->csets[s];
+        c.X = nullptr;
+        c.mean = (double *)p->mean_d.p + (int64_t)s * n;
+        c.Xc = (char *)p->staged_d.p + st_off[s];
+        c.part = (double *)p->part_d.p + part_off[s];
+        c.pad = 0;
+        p->sets[s].X = c.Xc;
+        SetRed &r = p->setred[s];
+        r.stride = off;
+        r.t = p->t[s];
+        for (int k = 0; k < MAXD - 1; ++k) r.kappa[k] = nullptr;
+        r.stamp = (unsigned long long *)p->stamps_d.p + 1 + s;
+    }
+    int64_t max_nst = 1;
+    for (int s = 0; s < n_sets; ++s) max_nst = std::max(max_nst, (p->t[s] + KT - 1) / KT);
+    p->stage_blocks = (int)std::min<int64_t>(max_nst, 64);
+    load_tune_file();
+    auto tk = g_tuned.find(std::make_tuple(n, b, 2, d_max, (int)prec, -(int64_t)n_sets));
+    const int shape = tk != g_tuned.end() ? tk->second.shape : default_shape(prec);
+    const int target = tk != g_tuned.end() ? tk->second.target : 16384;
+    if ((st = batch_layout(*p, shape, target))) return st;
+    HIP_TRY(hipMalloc(&p->cset_d.p, sizeof(CenterSet) * n_sets));
+    HIP_TRY(hipMalloc(&p->setred_d.p, sizeof(SetRed) * n_sets));
+    HIP_TRY(hipHostMalloc((void **)&p->h_cset, sizeof(CenterSet) * n_sets, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&p->h_setred, sizeof(SetRed) * n_sets, hipHostMallocDefault));
+    HIP_TRY(hipEventCreateWithFlags(&p->copied, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&p->ready, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
+    HIP_TRY(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+    *plan = p.release();
+    return CUM_OK;
+}
+
+cum_status cum_batch_run(cum_batch *p, const double *const *X_i, double *const *kappa, double *const *mean,
+                         void *stream) {
+    if (!p || !X_i || !kappa) return fail(CUM_EINVAL, "NULL argument");
+    const int nk = p->d_max - 1;
+    for (int s = 0; s < p->nsets; ++s) {
+        if (!X_i[s]) return fail(CUM_EINVAL, "X_i[%d] is NULL", s);
+        for (int k = 0; k < nk; ++k)
+            if (!kappa[(int64_t)s * nk + k]) return fail(CUM_EINVAL, "kappa[%d] is NULL", s * nk + k);
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t user = (hipStream_t)stream;
+    // the pinned tables may still be read by the previous run's copies
+    if (p->pending_copy) HIP_TRY(hipEventSynchronize(p->copied));
+    for (int s = 0; s < p->nsets; ++s) {
+        p->h_cset[s] = p->csets[s];
+        p->h_cset[s].X = X_i[s];
+        if (mean && mean[s]) p->h_cset[s].mean = mean[s];
+        p->h_setred[s] = p->setred[s];
+        for (int k = 0; k < nk; ++k) p->h_setred[s].kappa[k] = kappa[(int64_t)s * nk + k];
+    }
+    // order after the caller's stream, run on the plan's stream, order the caller after it
+    HIP_TRY(hipEventRecord(p->ready, user));
+    HIP_TRY(hipStreamWaitEvent(p->stream, p->ready, 0));
+    HIP_TRY(hipMemcpyAsync(p->cset_d.p, p->h_cset, sizeof(CenterSet) * p->nsets, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->setred_d.p, p->h_setred, sizeof(SetRed) * p->nsets, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipEventRecord(p->copied, p->stream));
+    p->pending_copy = true;
+    if (!p->exec) {
+        HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+        cum_status st = batch_enqueue(*p, p->stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(p->stream, &g);
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(CUM_EHIP, "graph capture: %s", hipGetErrorString(e));
+        p->graph = g;
+        HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    }
+    HIP_TRY(timed(CUM_KIND_BATCH, p->stream, [&] { return hipGraphLaunch(p->exec, p->stream); }));
+    HIP_TRY(hipEventRecord(p->done, p->stream));
+    HIP_TRY(hipStreamWaitEvent(user, p->done, 0));
+    return CUM_OK;
+}
+
+cum_status cum_batch_timestamps(cum_batch *p, uint64_t *start, uint64_t *ticks, double *hz) {
+    if (!p || !start || !ticks || !hz) return fail(CUM_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    std::vector<unsigned long long> h(p->nsets + 1);
+    HIP_TRY(hipMemcpy(h.data(), p->stamps_d.p, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    *start = h[0];
+    for (int s = 0; s < p->nsets; ++s) ticks[s] = h[1 + s];
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    *hz = khz * 1000.0;
+    return CUM_OK;
+}
+
+// Time the moment launch of every candidate (tile shape x work-item target)
+// on the batch's data and keep the fastest; the graph is captured again on
+// the next run.
+cum_status cum_batch_autotune(cum_batch *p, const double *const *X_i, cum_tuning *best) {
+    if (!p || !X_i) return fail(CUM_EINVAL, "NULL argument");
+    std::vector<double *> kap((size_t)p->nsets * (p->d_max - 1));
+    // outputs of the trial runs go to a scratch buffer shared by all datasets
+    DevBuf scratch;
+    HIP_TRY(hipMalloc(&scratch.p, (size_t)p->stride * sizeof(double)));
+    for (int s = 0; s < p->nsets; ++s)
+        for (int d = 2; d <= p->d_max; ++d) kap[(size_t)s * (p->d_max - 1) + d - 2] = (double *)scratch.p + p->out_off[d - 2];
+    const int shapes[] = {TS_1x1, TS_2x1};
+    const int targets[] = {4096, 16384, 65536};
+    float best_ms = 1e30f;
+    int best_shape = p->shape, best_target = 16384;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    cum_status st = CUM_OK;
+    for (int sh : shapes)
+        for (int tg : targets) {
+            {
+                std::lock_guard<std::mutex> lk(g_mu);
+                if ((st = batch_layout(*p, sh, tg))) break;
+            }
+            float ms_best = 1e30f;
+            for (int rep = 0; rep < 3 && !st; ++rep) {
+                if ((st = cum_batch_run(p, X_i, kap.data(), nullptr, nullptr))) break;
+                HIP_TRY(hipStreamSynchronize(p->stream));
+                HIP_TRY(hipEventRecord(e0, p->stream));
+                HIP_TRY(hipGraphLaunch(p->exec, p->stream));
+                HIP_TRY(hipEventRecord(e1, p->stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                ms_best = std::min(ms_best, ms);
+            }
+            if (st) break;
+            if (ms_best < best_ms) {
+                best_ms = ms_best;
+                best_shape = sh;
+                best_target = tg;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(hipDeviceSynchronize());
+    if (st) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((st = batch_layout(*p, best_shape, best_target))) return st;
+    g_tuned[std::make_tuple(p->n, p->b, 2, p->d_max, p->prec, -(int64_t)p->nsets)] = Tuning{best_shape, best_target};
+    save_tune_file();
+    if (best) {
+        best->shape = best_shape;
+        best->target_items = best_target;
+        best->ms = best_ms;
+    }
+    return CUM_OK;
+}
+
+cum_status cum_batch_destroy(cum_batch *plan) {
+    batch_free(plan);
+    return CUM_OK;
+}
+
 
 }  // extern "C"

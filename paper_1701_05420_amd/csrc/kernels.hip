@@ -137,18 +137,6 @@ __global__ __launch_bounds__(256) void batch_mean_kernel(const CenterSet *sets, 
     mean_body(cs.part, cs.groups, n, cs.t, cs.mean, blockIdx.x);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void batch_center_kernel(const CenterSet *sets, int n) {
-    const CenterSet cs = sets[blockIdx.y];
-    const int64_t total = cs.t * n;
-    T *Xc = reinterpret_cast<T *>(cs.Xc);
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        const int64_t l = e / n;
-        const int i = (int)(e - l * n);
-        Xc[e] = (T)(cs.X[l * n + i] - cs.mean[i]);
-    }
-}
-
 __global__ void stamp_kernel(unsigned long long *where) {
     if (threadIdx.x == 0) *where = wall_clock64();
 }
@@ -214,6 +202,36 @@ hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const doub
             hipLaunchKernelGGL((stage_kernel<float, float, false>), dim3(grid), dim3(256), 0, s, (const float *)X, t,
                                n, ldx, nullptr, (float *)Xst, KT, KTP, nst);
     }
+    return hipGetLastError();
+}
+
+// Batched: grid (blocks per dataset, datasets); each block walks its
+// dataset's stages with stride gridDim.x.
+template <typename TO>
+__global__ __launch_bounds__(256) void batch_stage_kernel(const CenterSet *sets, int n, int KT, int KTP) {
+    const CenterSet cs = sets[blockIdx.y];
+    const int64_t nst = (cs.t + KT - 1) / KT;
+    for (int64_t st = blockIdx.x; st < nst; st += gridDim.x)
+        stage_body<double, TO, true>(cs.X, cs.t, n, n, cs.mean, reinterpret_cast<TO *>(cs.Xc), KT, KTP, st);
+}
+
+hipError_t launch_batch_stage(const CenterSet *sets, int nsets, int n, int prec, int blocks_per_set, hipStream_t s) {
+    const int KT = stage_kt(prec), KTP = stage_pitch(prec);
+    if (prec == P_F64)
+        hipLaunchKernelGGL(batch_stage_kernel<double>, dim3(blocks_per_set, nsets), dim3(256), 0, s, sets, n, KT, KTP);
+    else
+        hipLaunchKernelGGL(batch_stage_kernel<float>, dim3(blocks_per_set, nsets), dim3(256), 0, s, sets, n, KT, KTP);
+    return hipGetLastError();
+}
+
+// Zero the per-dataset finalisation stamps and record the start time.
+__global__ void batch_stamp_kernel(unsigned long long *stamps, int nsets) {
+    for (int i = threadIdx.x; i < nsets; i += blockDim.x) stamps[1 + i] = 0ull;
+    if (threadIdx.x == 0) stamps[0] = wall_clock64();
+}
+
+hipError_t launch_batch_stamp(unsigned long long *stamps, int nsets, hipStream_t s) {
+    hipLaunchKernelGGL(batch_stamp_kernel, dim3(1), dim3(256), 0, s, stamps, nsets);
     return hipGetLastError();
 }
 
@@ -349,6 +367,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev &til
 
     d4 acc64[WM][WN][RH][RH];
     f16v acc[WM][WN];
+    f16v acc2[WM][WN];  // three-term split: the five small cross products
     double dacc[WM][WN][16];
     if constexpr (PREC == P_F64) {
 #pragma unroll
@@ -367,6 +386,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev &til
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     acc[i][j][k] = 0.f;
+                    acc2[i][j][k] = 0.f;
                     dacc[i][j][k] = 0.0;
                 }
     }
@@ -487,8 +507,9 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev &til
                             split2(v, Bs[j][0], Bs[j][1]);
                     }
                     // cross products of the split terms: all 4 for two terms; for three
-                    // terms the 6 of combined weight >= 2^-16 (hh, hm, mh, hl, lh, mm);
-                    // smallest first
+                    // terms the 6 of combined weight >= 2^-16 (hh, hm, mh, hl, lh, mm),
+                    // hh in its own accumulator so that the five small products do
+                    // not add roundings at the full magnitude; smallest first
                     constexpr int NP = (NS == 3) ? 6 : 4;
                     constexpr int PA[4] = {0, 0, 1, 1};        // hh, hl, lh, ll
                     constexpr int PB[4] = {0, 1, 0, 1};
@@ -503,8 +524,12 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev &til
                                 if (vmask >> (i * WN + j) & 1u) {
                                     const int ia = (NS == 3) ? PA3[pr] : PA[pr & 3];
                                     const int ib = (NS == 3) ? PB3[pr] : PB[pr & 3];
-                                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(As[i][ia], Bs[j][ib],
-                                                                                        acc[i][j], 0, 0, 0);
+                                    if (NS == 3 && pr > 0)
+                                        acc2[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(As[i][ia], Bs[j][ib],
+                                                                                             acc2[i][j], 0, 0, 0);
+                                    else
+                                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(As[i][ia], Bs[j][ib],
+                                                                                            acc[i][j], 0, 0, 0);
                                 }
                     }
                 }
@@ -521,7 +546,12 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev &til
                     for (int j = 0; j < WN; ++j)
 #pragma unroll
                         for (int q = 0; q < 16; ++q) {
-                            dacc[i][j][q] += (double)acc[i][j][q];
+                            if constexpr (PREC == P_BF16X3) {
+                                dacc[i][j][q] += (double)acc[i][j][q] + (double)acc2[i][j][q];
+                                acc2[i][j][q] = 0.f;
+                            } else {
+                                dacc[i][j][q] += (double)acc[i][j][q];
+                            }
                             acc[i][j][q] = 0.f;
                         }
             }
@@ -781,14 +811,6 @@ hipError_t launch_batch_colsum(const CenterSet *sets, int nsets, int max_groups,
 
 hipError_t launch_batch_mean(const CenterSet *sets, int nsets, int n, hipStream_t s) {
     hipLaunchKernelGGL(batch_mean_kernel, dim3(n, nsets), dim3(256), 0, s, sets, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_center(const CenterSet *sets, int nsets, int n, int prec, int blocks_per_set, hipStream_t s) {
-    if (prec == P_F64)
-        hipLaunchKernelGGL(batch_center_kernel<double>, dim3(blocks_per_set, nsets), dim3(256), 0, s, sets, n);
-    else
-        hipLaunchKernelGGL(batch_center_kernel<float>, dim3(blocks_per_set, nsets), dim3(256), 0, s, sets, n);
     return hipGetLastError();
 }
 

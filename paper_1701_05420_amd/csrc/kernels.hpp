@@ -51,7 +51,7 @@ struct CenterSet {
     const double *X;   // t x n, ld n
     int64_t t;
     double *mean;      // n
-    float *Xc;         // t x n FP32 (or double* when the precision is FP64)
+    void *Xc;          // staged layout (FP32, or FP64 for the FP64 path)
     double *part;      // groups x n x 2 partial sums
     int32_t groups;
     int32_t pad;
@@ -59,7 +59,8 @@ struct CenterSet {
 };
 hipError_t launch_batch_colsum(const CenterSet *sets, int nsets, int max_groups, int n, hipStream_t s);
 hipError_t launch_batch_mean(const CenterSet *sets, int nsets, int n, hipStream_t s);
-hipError_t launch_batch_center(const CenterSet *sets, int nsets, int n, int prec, int blocks_per_set, hipStream_t s);
+hipError_t launch_batch_stage(const CenterSet *sets, int nsets, int n, int prec, int blocks_per_set, hipStream_t s);
+hipError_t launch_batch_stamp(unsigned long long *stamps, int nsets, hipStream_t s);
 hipError_t launch_stamp(unsigned long long *where, hipStream_t s);
 
 }  // namespace cum
