@@ -188,7 +188,21 @@ def main():
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (planner defaults)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-dataset batched measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (to scale HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+
+        nbytes = 512 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 10}), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X (sharding across GPUs "
