@@ -150,7 +150,7 @@ cum_status cum_stored_offset(int n, int d, int b, const int32_t *idx /* host */,
  * size b by timing, Section 5.2; here b is the caller's storage choice and
  * the tuned knobs are the launch's):
  *   shape         work-group tile of one order's (rows x columns) product:
- *                 0 = 64 x 64, 2 = 128 x 64, 1 = 128 x 128 entries;
+ *                 0 = 64 x 64, 2 = 128 x 64 entries;
  *   target_items  about how many (tile, sample-chunk) work items to create;
  *                 it sets the sample chunk length, hence the split over
  *                 samples and the size of the FP64 partial-sum buffer.

@@ -343,8 +343,8 @@ static void order_tiles(const OrderPlan &o, int wm, int wn, int ord_index, std::
 }
 
 static void shape_dims(int shape, int &wm, int &wn) {
-    wm = (shape == TS_2x1 || shape == TS_2x2) ? 2 : 1;
-    wn = shape == TS_2x2 ? 2 : 1;
+    wm = shape == TS_2x1 ? 2 : 1;
+    wn = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -575,7 +575,7 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
     ma.n = c->n;
     ma.pad = 0;
     if (c->nitems > 0)
-        HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, ma, (int)c->nitems, s); }));
+        HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, c->dhi, ma, (int)c->nitems, s); }));
     // reduction (+ recursion) in pairs of orders {d, d+1}: order d needs
     // cumulants up to d-2 only, so a pair depends only on earlier pairs
     const RedOrder *red_d = (const RedOrder *)c->red_d.p;
@@ -791,7 +791,7 @@ cum_status cum_plan_check(int n, int d, int b) {
     if ((st = build_order(n, b, d, o))) return st;  // host tables only, nothing uploaded
     const int64_t be = ipow64(b, d);
     auto T = sorted_tuples(o.nbar, d);
-    for (int shape : {TS_1x1, TS_2x1, TS_2x2}) {
+    for (int shape : {TS_1x1, TS_2x1}) {
         int wm, wn;
         shape_dims(shape, wm, wn);
         std::vector<HostTile> tiles;
@@ -844,7 +844,7 @@ cum_status cum_set_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, con
         g_tuned.erase(key);
         return CUM_OK;
     }
-    if (tune->shape != TS_1x1 && tune->shape != TS_2x1 && tune->shape != TS_2x2)
+    if (tune->shape != TS_1x1 && tune->shape != TS_2x1)
         return fail(CUM_EINVAL, "unknown tile shape %d", tune->shape);
     if (tune->target_items < 1) return fail(CUM_EINVAL, "target_items must be >= 1");
     g_tuned[key] = Tuning{tune->shape, tune->target_items};
@@ -1106,7 +1106,7 @@ static cum_status batch_enqueue(cum_batch &p, hipStream_t s) {
     ma.nitems = p.nitems;
     ma.sets = (const SetDev *)p.sets_d.p;
     ma.n = p.n;
-    if (p.nitems > 0) HIP_TRY(launch_moment(p.prec, p.shape, ma, (int)p.nitems, s));
+    if (p.nitems > 0) HIP_TRY(launch_moment(p.prec, p.shape, p.d_max, ma, (int)p.nitems, s));
     const RedOrder *red_d = (const RedOrder *)p.red_d.p;
     for (int d = 2; d <= p.d_max; d += 2) {
         RedArgs ra;

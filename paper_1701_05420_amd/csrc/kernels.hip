@@ -599,7 +599,10 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev &til
         }
 }
 
-template <int PREC, int WM, int WN>
+// DMAX: the largest order the launch holds (4, 6 or 8).  Only the prefix /
+// suffix lengths up to it are compiled in, so a launch of low orders gets
+// the register allocation of its own bodies.
+template <int PREC, int WM, int WN, int DMAX>
 __global__ __launch_bounds__(256, 2) void moment_kernel(MomentArgs a) {
     extern __shared__ __align__(16) char lds[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -613,39 +616,50 @@ __global__ __launch_bounds__(256, 2) void moment_kernel(MomentArgs a) {
             case 1 * 8 + 1: moment_item<PREC, WM, WN, 1, 1>(item, tile, od, sd, lds, a.n, wave); break;
             case 1 * 8 + 2: moment_item<PREC, WM, WN, 1, 2>(item, tile, od, sd, lds, a.n, wave); break;
             case 2 * 8 + 2: moment_item<PREC, WM, WN, 2, 2>(item, tile, od, sd, lds, a.n, wave); break;
-            case 2 * 8 + 3: moment_item<PREC, WM, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave); break;
-            case 3 * 8 + 3: moment_item<PREC, WM, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave); break;
-            case 3 * 8 + 4: moment_item<PREC, WM, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave); break;
-            case 4 * 8 + 4: moment_item<PREC, WM, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave); break;
+            case 2 * 8 + 3:
+                if constexpr (DMAX >= 5) moment_item<PREC, WM, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave);
+                break;
+            case 3 * 8 + 3:
+                if constexpr (DMAX >= 6) moment_item<PREC, WM, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave);
+                break;
+            case 3 * 8 + 4:
+                if constexpr (DMAX >= 7) moment_item<PREC, WM, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave);
+                break;
+            case 4 * 8 + 4:
+                if constexpr (DMAX >= 8) moment_item<PREC, WM, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave);
+                break;
             default: break;
         }
     }
 }
 
+template <int PREC, int WM, int WN>
+static void launch_moment_dmax(int dmax, const MomentArgs &a, int grid, int lds, hipStream_t s) {
+    if (dmax <= 4)
+        hipLaunchKernelGGL((moment_kernel<PREC, WM, WN, 4>), dim3(grid), dim3(256), lds, s, a);
+    else if (dmax <= 6)
+        hipLaunchKernelGGL((moment_kernel<PREC, WM, WN, 6>), dim3(grid), dim3(256), lds, s, a);
+    else
+        hipLaunchKernelGGL((moment_kernel<PREC, WM, WN, 8>), dim3(grid), dim3(256), lds, s, a);
+}
+
 template <int PREC>
-static hipError_t launch_moment_prec(int shape, const MomentArgs &a, int grid, hipStream_t s) {
+static hipError_t launch_moment_prec(int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s) {
     const int lds = lds_bytes_moment(PREC, a.n);
     switch (shape) {
-        case TS_1x1:
-            hipLaunchKernelGGL((moment_kernel<PREC, 1, 1>), dim3(grid), dim3(256), lds, s, a);
-            break;
-        case TS_2x1:
-            hipLaunchKernelGGL((moment_kernel<PREC, 2, 1>), dim3(grid), dim3(256), lds, s, a);
-            break;
-        case TS_2x2:
-            hipLaunchKernelGGL((moment_kernel<PREC, 2, 2>), dim3(grid), dim3(256), lds, s, a);
-            break;
+        case TS_1x1: launch_moment_dmax<PREC, 1, 1>(dmax, a, grid, lds, s); break;
+        case TS_2x1: launch_moment_dmax<PREC, 2, 1>(dmax, a, grid, lds, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_moment(int prec, int shape, const MomentArgs &a, int grid, hipStream_t s) {
+hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s) {
     switch (prec) {
-        case P_F64: return launch_moment_prec<P_F64>(shape, a, grid, s);
-        case P_F32: return launch_moment_prec<P_F32>(shape, a, grid, s);
-        case P_BF16X2: return launch_moment_prec<P_BF16X2>(shape, a, grid, s);
-        default: return launch_moment_prec<P_BF16X3>(shape, a, grid, s);
+        case P_F64: return launch_moment_prec<P_F64>(shape, dmax, a, grid, s);
+        case P_F32: return launch_moment_prec<P_F32>(shape, dmax, a, grid, s);
+        case P_BF16X2: return launch_moment_prec<P_BF16X2>(shape, dmax, a, grid, s);
+        default: return launch_moment_prec<P_BF16X3>(shape, dmax, a, grid, s);
     }
 }
 

@@ -31,13 +31,13 @@ struct RedArgs {
 };
 
 // Work-group tile shapes: WM x WN blocks of 32 x 32 per wave, 2 x 2 waves.
-enum TileShape { TS_1x1 = 0, TS_2x2 = 1, TS_2x1 = 2 };
+enum TileShape { TS_1x1 = 0, TS_2x1 = 2 };
 
 int lds_bytes_moment(int prec, int n);
 // row-major data (FP64 with ldx, or FP32 with ldx) -> staged layout, optionally centred
 hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xst, int prec,
                         bool center, bool in_f64, hipStream_t s);
-hipError_t launch_moment(int prec, int shape, const MomentArgs &a, int grid, hipStream_t s);
+hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s);
 hipError_t launch_reduce(const RedArgs &a, int nsets, hipStream_t s);
 hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,
                          hipStream_t s);

@@ -203,7 +203,7 @@ def test_autotune_and_tuned_configs(dev, orc):
     offs_idx = {d: stored_sample(orc, 24, d, 4, 200, seed=d) for d in range(2, 6)}
     want = {d: orc.cumulant_at(Xc, offs_idx[d][1]) for d in offs_idx}
     for prec in PRECS:
-        for shape in ["64x64", "128x64", "128x128"]:
+        for shape in ["64x64", "128x64"]:
             for target in [256, 1024, 4096]:
                 say(f"tuned prec={prec} shape={shape} target={target}")
                 pc.set_tuning(30_000, 24, 5, 4, prec, shape, target)
@@ -217,5 +217,5 @@ def test_autotune_and_tuned_configs(dev, orc):
         pc.set_tuning(30_000, 24, 5, 4, prec, None)
         best = pc.autotune(Xd, 5, 4, prec)
         say(f"autotune {prec}: {best}")
-        assert best["shape"] in (0, 1, 2) and best["ms"] > 0
+        assert best["shape"] in (0, 2) and best["ms"] > 0
         pc.set_tuning(30_000, 24, 5, 4, prec, None)
