@@ -149,8 +149,9 @@ cum_status cum_stored_offset(int n, int d, int b, const int32_t *idx /* host */,
  * Autotuning of the contraction's launch shape (the paper picks its block
  * size b by timing, Section 5.2; here b is the caller's storage choice and
  * the tuned knobs are the launch's):
- *   shape         work-group tile of one order's (rows x columns) product:
- *                 0 = 64 x 64, 2 = 128 x 64 entries;
+ *   shape         one wave's task in one order's (rows x columns) product:
+ *                 0 = 32 x 32, 2 = 32 x 64 entries (four tasks per
+ *                 work-group, packed so that waves have equal work);
  *   target_items  about how many (tile, sample-chunk) work items to create;
  *                 it sets the sample chunk length, hence the split over
  *                 samples and the size of the FP64 partial-sum buffer.

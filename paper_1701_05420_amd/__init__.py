@@ -34,7 +34,7 @@ EXPORTS = [
     "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning",
     "cum_batch_autotune", "cum_status_str", "cum_last_error",
 ]
-SHAPES = {"64x64": 0, "128x64": 2}
+SHAPES = {"32x32": 0, "32x64": 2}
 
 
 class Tuning(ctypes.Structure):

@@ -183,7 +183,8 @@ struct OrderPlan {
     int n = 0, b = 0, d = 0, p = 0, q = 0, nbar = 0, nr = 0, nc = 0;
     int64_t nblocks = 0, elems = 0;
     std::vector<Feat> rows, cols;
-    std::vector<int32_t> rb_vmin, cb_wmax;
+    std::vector<int32_t> rb_vmin, cb_wmax;  // per 32-row / 32-column block
+    std::vector<int32_t> rv16, cw16;        // per 16-row / 16-column block
     std::vector<int64_t> H;
     std::vector<uint8_t> tuples;
     std::vector<uint16_t> parts;  // npart x MAXPARTS
@@ -278,6 +279,16 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
         for (int c = cb * FEAT_BLOCK; c < std::min(nc_real, (cb + 1) * FEAT_BLOCK); ++c) w = std::max(w, o.cols[c].blk);
         o.cb_wmax.push_back(w);
     }
+    for (int rb = 0; rb < o.nr / 16; ++rb) {
+        int32_t v = INT32_MAX;
+        for (int r = rb * 16; r < std::min(nr_real, (rb + 1) * 16); ++r) v = std::min(v, o.rows[r].blk);
+        o.rv16.push_back(v);
+    }
+    for (int cb = 0; cb < o.nc / 16; ++cb) {
+        int32_t w = -1;
+        for (int c = cb * 16; c < std::min(nc_real, (cb + 1) * 16); ++c) w = std::max(w, o.cols[c].blk);
+        o.cw16.push_back(w);
+    }
     o.H.assign((size_t)nbar * nbar, 0);
     for (int v = 0; v < nbar; ++v)
         for (int w = v; w < nbar; ++w) o.H[(size_t)v * nbar + w] = bd * rank_term(nbar, d, p, v, w);
@@ -297,8 +308,8 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
 static cum_status upload_order(OrderPlan &o) {
     if (o.uploaded) return CUM_OK;
     cum_status st;
-    if ((st = upload(o.rows_d, o.rows)) || (st = upload(o.cols_d, o.cols)) || (st = upload(o.rbv_d, o.rb_vmin)) ||
-        (st = upload(o.cbw_d, o.cb_wmax)) || (st = upload(o.H_d, o.H)) || (st = upload(o.tuples_d, o.tuples)) ||
+    if ((st = upload(o.rows_d, o.rows)) || (st = upload(o.cols_d, o.cols)) || (st = upload(o.rbv_d, o.rv16)) ||
+        (st = upload(o.cbw_d, o.cw16)) || (st = upload(o.H_d, o.H)) || (st = upload(o.tuples_d, o.tuples)) ||
         (st = upload(o.parts_d, o.parts)))
         return st;
     o.uploaded = true;
@@ -323,29 +334,50 @@ static cum_status get_order(int n, int b, int d, OrderPlan **out) {
     return CUM_OK;
 }
 
-// Work-group tiles of one order: WM x WN 32-blocks per wave, 2 x 2 waves.
-// Only tiles holding a stored entry are kept; cost = stored 32-blocks.
+// Work-group tiles of one order.  A wave task is a 32-row block by WN
+// consecutive 32-column blocks holding at least one stored entry; its cost
+// is the number of stored 16 x 16 sub-blocks.  Tasks are sorted by cost and
+// packed four to a work-group, so the four waves of a work-group have
+// nearly equal work and no wave sits idle except in the order's last tile.
 struct HostTile {
     TileDev t;
-    int cost;
+    int cost;  // the largest task cost of the tile
 };
 
-static void order_tiles(const OrderPlan &o, int wm, int wn, int ord_index, std::vector<HostTile> &out) {
-    const int TM = 2 * wm * 32, TN = 2 * wn * 32;
-    for (int r0 = 0; r0 < o.nr; r0 += TM)
-        for (int c0 = 0; c0 < o.nc; c0 += TN) {
-            int cost = 0;
-            for (int rb = r0 / 32; rb < std::min(o.nr, r0 + TM) / 32; ++rb)
-                for (int cb = c0 / 32; cb < std::min(o.nc, c0 + TN) / 32; ++cb)
-                    if (o.rb_vmin[rb] <= o.cb_wmax[cb]) ++cost;
-            if (cost) out.push_back({{ord_index, r0, c0, 0}, cost});
+static void order_tiles(const OrderPlan &o, int wn, int ord_index, std::vector<HostTile> &out) {
+    struct Task {
+        WaveTask w;
+        int cost;
+    };
+    std::vector<Task> tasks;
+    const int nrb = o.nr / 32, ncb = o.nc / 32;
+    for (int rb = 0; rb < nrb; ++rb)
+        for (int cb = 0; cb < ncb; cb += wn) {
+            int mask = 0, cost = 0;
+            for (int j = 0; j < wn && cb + j < ncb; ++j) {
+                if (o.rb_vmin[rb] > o.cb_wmax[cb + j]) continue;
+                mask |= 1 << j;
+                for (int h = 0; h < 2; ++h)
+                    for (int g = 0; g < 2; ++g)
+                        if (o.rv16[2 * rb + h] <= o.cw16[2 * (cb + j) + g]) ++cost;
+            }
+            if (mask) tasks.push_back({{rb * 32, cb * 32, mask, 0}, cost});
         }
+    std::stable_sort(tasks.begin(), tasks.end(), [](const Task &x, const Task &y) { return x.cost > y.cost; });
+    for (size_t i = 0; i < tasks.size(); i += 4) {
+        HostTile ht;
+        memset(&ht.t, 0, sizeof ht.t);
+        ht.t.ord = ord_index;
+        ht.cost = 0;
+        for (size_t k = i; k < std::min(tasks.size(), i + 4); ++k) {
+            ht.t.task[ht.t.ntask++] = tasks[k].w;
+            ht.cost = std::max(ht.cost, tasks[k].cost);
+        }
+        out.push_back(ht);
+    }
 }
 
-static void shape_dims(int shape, int &wm, int &wn) {
-    wm = shape == TS_2x1 ? 2 : 1;
-    wn = 1;
-}
+static int shape_wn(int shape) { return shape == TS_1x2 ? 2 : 1; }
 
 // ---------------------------------------------------------------------------
 // call plan: all orders dlo..dhi of one (n, b), one precision and tile shape,
@@ -374,8 +406,8 @@ static cum_status upload_call(CallPlan &c) {
         if ((st = upload_order(*o))) return st;
         c.ods[i].rows = (const Feat *)o->rows_d.p;
         c.ods[i].cols = (const Feat *)o->cols_d.p;
-        c.ods[i].rb_vmin = (const int32_t *)o->rbv_d.p;
-        c.ods[i].cb_wmax = (const int32_t *)o->cbw_d.p;
+        c.ods[i].rv16 = (const int32_t *)o->rbv_d.p;
+        c.ods[i].cw16 = (const int32_t *)o->cbw_d.p;
         c.ods[i].H = (const int64_t *)o->H_d.p;
         c.red[i].tuples = (const uint8_t *)o->tuples_d.p;
         c.red[i].parts = (const uint16_t *)o->parts_d.p;
@@ -430,7 +462,7 @@ static void save_tune_file() {
     fclose(fp);
 }
 
-static int default_shape(int prec) { return prec == P_F32 ? TS_1x1 : TS_2x1; }
+static int default_shape(int prec) { return prec == P_F32 ? TS_1x1 : TS_1x2; }
 constexpr int DEFAULT_TARGET = 1024;
 
 static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int shape, int target, int64_t t,
@@ -450,8 +482,7 @@ static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int sha
     c->shape = shape;
     c->t = t;
     c->nstages = (t + stage_kt(prec) - 1) / stage_kt(prec);
-    int wm, wn;
-    shape_dims(shape, wm, wn);
+    const int wn = shape_wn(shape);
     std::vector<HostTile> tiles;
     int64_t off = 0;
     for (int d = dlo; d <= dhi; ++d) {
@@ -463,8 +494,8 @@ static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int sha
         OrderDev od;
         od.rows = nullptr;
         od.cols = nullptr;
-        od.rb_vmin = nullptr;
-        od.cb_wmax = nullptr;
+        od.rv16 = nullptr;
+        od.cw16 = nullptr;
         od.H = nullptr;
         od.out_off = off;
         od.elems = o->elems;
@@ -477,7 +508,7 @@ static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int sha
         od.nc = o->nc;
         od.pad = 0;
         c->ods.push_back(od);
-        order_tiles(*o, wm, wn, d - dlo, tiles);
+        order_tiles(*o, wn, d - dlo, tiles);
         RedOrder ro;
         ro.tuples = nullptr;
         ro.parts = nullptr;
@@ -791,42 +822,48 @@ cum_status cum_plan_check(int n, int d, int b) {
     if ((st = build_order(n, b, d, o))) return st;  // host tables only, nothing uploaded
     const int64_t be = ipow64(b, d);
     auto T = sorted_tuples(o.nbar, d);
-    for (int shape : {TS_1x1, TS_2x1}) {
-        int wm, wn;
-        shape_dims(shape, wm, wn);
+    for (int shape : {TS_1x1, TS_1x2}) {
+        const int wn = shape_wn(shape);
         std::vector<HostTile> tiles;
-        order_tiles(o, wm, wn, 0, tiles);
+        order_tiles(o, wn, 0, tiles);
         std::vector<uint8_t> hits((size_t)o.elems, 0);
-        const int TM = 2 * wm * 32, TN = 2 * wn * 32;
-        for (const auto &ht : tiles) {
-            for (int r = ht.t.row0; r < std::min(o.nr, ht.t.row0 + TM); ++r)
-                for (int c = ht.t.col0; c < std::min(o.nc, ht.t.col0 + TN); ++c) {
-                    const Feat &fr = o.rows[r], &fc = o.cols[c];
-                    const bool stored = fr.blk <= fc.blk;
-                    const bool computed = o.rb_vmin[r / 32] <= o.cb_wmax[c / 32];
-                    if (stored && !computed)
-                        return fail(CUM_EINVAL, "d=%d: entry (%d,%d) lies in a skipped block", d, r, c);
-                    if (!stored) continue;
-                    const int64_t addr = fr.addr + fc.addr + o.H[(size_t)fr.blk * o.nbar + fc.blk];
-                    if (addr < 0 || addr >= o.elems) return fail(CUM_EINVAL, "d=%d: address %lld out of range", d, (long long)addr);
-                    if (hits[(size_t)addr]++) return fail(CUM_EINVAL, "d=%d: address %lld written twice", d, (long long)addr);
-                    // the variables multiplied there must be the ones stored there
-                    const auto &j = T[(size_t)(addr / be)];
-                    int64_t in = addr % be;
-                    int dig[CUM_MAX_ORDER];
-                    for (int k = d - 1; k >= 0; --k) {
-                        dig[k] = (int)(in % b);
-                        in /= b;
-                    }
-                    for (int k = 0; k < d; ++k) {
-                        int v = j[k] * b + dig[k];
-                        if (v > n) v = n;
-                        const int have = k < o.p ? fr.var[k] : fc.var[k - o.p];
-                        if (have != v)
-                            return fail(CUM_EINVAL, "d=%d: variable mismatch at address %lld", d, (long long)addr);
-                    }
+        for (const auto &ht : tiles)
+            for (int w = 0; w < ht.t.ntask; ++w) {
+                const WaveTask &wt = ht.t.task[w];
+                for (int j = 0; j < wn; ++j) {
+                    if (!(wt.mask >> j & 1)) continue;
+                    for (int r = wt.r0; r < wt.r0 + 32; ++r)
+                        for (int c = wt.c0 + 32 * j; c < std::min(o.nc, wt.c0 + 32 * j + 32); ++c) {
+                            const Feat &fr = o.rows[r], &fc = o.cols[c];
+                            const bool stored = fr.blk <= fc.blk;
+                            const bool computed = o.rv16[r / 16] <= o.cw16[c / 16];
+                            if (stored && !computed)
+                                return fail(CUM_EINVAL, "d=%d: entry (%d,%d) lies in a skipped block", d, r, c);
+                            if (!stored) continue;
+                            const int64_t addr = fr.addr + fc.addr + o.H[(size_t)fr.blk * o.nbar + fc.blk];
+                            if (addr < 0 || addr >= o.elems)
+                                return fail(CUM_EINVAL, "d=%d: address %lld out of range", d, (long long)addr);
+                            if (hits[(size_t)addr]++)
+                                return fail(CUM_EINVAL, "d=%d: address %lld written twice", d, (long long)addr);
+                            // the variables multiplied there must be the ones stored there
+                            const auto &jt = T[(size_t)(addr / be)];
+                            int64_t in = addr % be;
+                            int dig[CUM_MAX_ORDER];
+                            for (int k = d - 1; k >= 0; --k) {
+                                dig[k] = (int)(in % b);
+                                in /= b;
+                            }
+                            for (int k = 0; k < d; ++k) {
+                                int v = jt[k] * b + dig[k];
+                                if (v > n) v = n;
+                                const int have = k < o.p ? fr.var[k] : fc.var[k - o.p];
+                                if (have != v)
+                                    return fail(CUM_EINVAL, "d=%d: variable mismatch at address %lld", d,
+                                                (long long)addr);
+                            }
+                        }
                 }
-        }
+            }
         for (size_t e = 0; e < hits.size(); ++e)
             if (hits[e] != 1) return fail(CUM_EINVAL, "d=%d: address %zu never written", d, e);
     }
@@ -844,7 +881,7 @@ cum_status cum_set_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, con
         g_tuned.erase(key);
         return CUM_OK;
     }
-    if (tune->shape != TS_1x1 && tune->shape != TS_2x1)
+    if (tune->shape != TS_1x1 && tune->shape != TS_1x2)
         return fail(CUM_EINVAL, "unknown tile shape %d", tune->shape);
     if (tune->target_items < 1) return fail(CUM_EINVAL, "target_items must be >= 1");
     g_tuned[key] = Tuning{tune->shape, tune->target_items};
@@ -862,7 +899,7 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     if (!X || ldx < n) return fail(CUM_EINVAL, "bad X / ldx");
     std::lock_guard<std::mutex> lk(g_mu);
     hipStream_t s = (hipStream_t)stream;
-    const int shapes[] = {TS_1x1, TS_2x1};
+    const int shapes[] = {TS_1x1, TS_1x2};
     const int targets[] = {512, 1024, 2048, 4096};
     std::vector<CallPlan *> cands;
     size_t part_max = 0;
@@ -1037,11 +1074,10 @@ static std::vector<Item> batch_items(const cum_batch &p) {
 // (Re)build the tiles, chunking and items for a shape and target, and the
 // per-dataset records that depend on them.
 static cum_status batch_layout(cum_batch &p, int shape, int target) {
-    int wm, wn;
-    shape_dims(shape, wm, wn);
+    const int wn = shape_wn(shape);
     p.shape = shape;
     p.tiles.clear();
-    for (size_t i = 0; i < p.orders.size(); ++i) order_tiles(*p.orders[i], wm, wn, (int)i, p.tiles);
+    for (size_t i = 0; i < p.orders.size(); ++i) order_tiles(*p.orders[i], wn, (int)i, p.tiles);
     std::stable_sort(p.tiles.begin(), p.tiles.end(), [](const HostTile &x, const HostTile &y) { return x.cost > y.cost; });
     const int KT = stage_kt(p.prec);
     int64_t total_st = 0, max_st = 1;
@@ -1150,8 +1186,8 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
         OrderDev od;
         od.rows = (const Feat *)o->rows_d.p;
         od.cols = (const Feat *)o->cols_d.p;
-        od.rb_vmin = (const int32_t *)o->rbv_d.p;
-        od.cb_wmax = (const int32_t *)o->cbw_d.p;
+        od.rv16 = (const int32_t *)o->rbv_d.p;
+        od.cw16 = (const int32_t *)o->cbw_d.p;
         od.H = (const int64_t *)o->H_d.p;
         od.out_off = off;
         od.elems = o->elems;
@@ -1308,7 +1344,7 @@ cum_status cum_batch_autotune(cum_batch *p, const double *const *X_i, cum_tuning
     HIP_TRY(hipMalloc(&scratch.p, (size_t)p->stride * sizeof(double)));
     for (int s = 0; s < p->nsets; ++s)
         for (int d = 2; d <= p->d_max; ++d) kap[(size_t)s * (p->d_max - 1) + d - 2] = (double *)scratch.p + p->out_off[d - 2];
-    const int shapes[] = {TS_1x1, TS_2x1};
+    const int shapes[] = {TS_1x1, TS_1x2};
     const int targets[] = {4096, 16384, 65536};
     float best_ms = 1e30f;
     int best_shape = p->shape, best_target = 16384;

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -238,17 +239,18 @@ hipError_t launch_batch_stamp(unsigned long long *stamps, int nsets, hipStream_t
 // ---------------------------------------------------------------------------
 // Block moment contraction.
 //
-// A work item is one work-group tile (2 x 2 waves, each WM x WN blocks of
-// 32 x 32 entries) of one order's (prefix rows) x (suffix columns) product,
-// over one chunk of stages of one dataset.  Each stage is copied from HBM to
+// A work item is one work-group of four wave tasks (each a 32-row block by
+// WN 32-column blocks of one order's (prefix rows) x (suffix columns)
+// product, packed on the host so that no wave is idle) over one chunk of
+// stages of one dataset.  Each stage is copied from HBM to
 // LDS by the DMA path (global_load_lds, 16 bytes per lane, no registers),
 // double-buffered.  Every lane forms its Khatri-Rao operand values from the
 // staged samples -- the product of the prefix (or suffix) variables of its
 // row (or column) -- reading VEC consecutive samples per variable with one
 // 16-byte LDS read.  The sample order inside a stage is a free choice of the
 // sum, so lane group g of an MFMA takes samples g*VEC .. g*VEC+VEC-1 of each
-// group of steps.  32 x 32 blocks with no stored entry (v > w everywhere) are
-// skipped per wave.  The chunk's sums go, in FP64, to the chunk's slice of
+// group of steps.  16 x 16 sub-blocks with no stored entry (v > w everywhere)
+// are skipped per wave.  The chunk's sums go, in FP64, to the chunk's slice of
 // the partial buffer at each entry's block-storage offset.
 // ---------------------------------------------------------------------------
 template <int PREC>
@@ -313,83 +315,76 @@ __device__ __forceinline__ void split3(const float *v, bf8 &hi, bf8 &mid, bf8 &l
 
 typedef double d2 __attribute__((ext_vector_type(2)));
 
-template <int PREC, int WM, int WN, int P, int Q>
-__device__ __forceinline__ void moment_item(const Item &item, const TileDev &tile, const OrderDev &od,
+template <int PREC, int WN, int P, int Q>
+__device__ __forceinline__ void moment_item(const Item &item, const TileDev *tile, const OrderDev &od,
                                             const SetDev &sd, char *lds, int n, int wave) {
     typedef typename PT<PREC>::T T;
     constexpr int KT = PT<PREC>::KT, KTP = PT<PREC>::KTP;
-    constexpr int RH = (PREC == P_F64) ? 2 : 1;  // operand rows per lane per 32-block
+    constexpr bool BF = PREC >= P_BF16X2;
+    constexpr int NS = (PREC == P_BF16X3) ? 3 : 2;  // split terms (BF16 paths)
+    // samples per step group: lane group g (= lane / 16) holds VEC consecutive samples
+    constexpr int VEC = (PREC == P_F64) ? 2 : (PREC == P_F32 ? 4 : 8);
+    constexpr int STEP = 4 * VEC;
     const int tid = threadIdx.x, lane = tid & 63;
-    const int wy = wave >> 1, wx = wave & 1;
     const int stage_bytes = (n + 1) * KTP * (int)sizeof(T);
-    const int rbase = tile.row0 + wy * (WM * 32), cbase = tile.col0 + wx * (WN * 32);
-    // first sample of this lane's group inside a step group
-    const int soff = (PREC == P_F64) ? 2 * (lane >> 4) : (PREC == P_F32 ? 4 * (lane >> 5) : 8 * (lane >> 5));
+    const bool active = wave < tile->ntask;
+    const WaveTask wt = tile->task[active ? wave : 0];
+    const int rbase = wt.r0, cbase = wt.c0;
+    const int soff = VEC * (lane >> 4);
 
-    // which of this wave's 32 x 32 blocks hold stored entries (wave-uniform)
+    // which 16 x 16 sub-blocks of this wave's 32 x (32*WN) task hold stored
+    // entries (wave-uniform): bit (j*4 + h*2 + g)
     unsigned vmask = 0;
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+        for (int j = 0; j < WN; ++j)
+            if (wt.mask >> j & 1)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            const int r0 = rbase + i * 32, c0 = cbase + j * 32;
-            if (r0 < od.nr && c0 < od.nc && od.rb_vmin[r0 >> 5] <= od.cb_wmax[c0 >> 5]) vmask |= 1u << (i * WN + j);
-        }
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int g = 0; g < 2; ++g)
+                        if (od.rv16[(rbase >> 4) + h] <= od.cw16[((cbase + 32 * j) >> 4) + g])
+                            vmask |= 1u << (j * 4 + h * 2 + g);
+    }
 
     // LDS offsets (in T) of this lane's operand variables, plus its sample offset
-    int roff[WM][RH][P], coff[WN][RH][Q];
+    int roff[2][P], coff[WN][2][Q];
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+    for (int h = 0; h < 2; ++h) {
+        const Feat f = od.rows[rbase + 16 * h + (lane & 15)];
 #pragma unroll
-        for (int h = 0; h < RH; ++h) {
-            const int r = rbase + i * 32 + (PREC == P_F64 ? h * 16 + (lane & 15) : (lane & 31));
-            Feat f;
-            if (r < od.nr)
-                f = od.rows[r];
-            else
-                for (int q = 0; q < MAXH; ++q) f.var[q] = (uint8_t)n;
-#pragma unroll
-            for (int q = 0; q < P; ++q) roff[i][h][q] = f.var[q] * KTP + soff;
-        }
+        for (int q = 0; q < P; ++q) roff[h][q] = f.var[q] * KTP + soff;
+    }
 #pragma unroll
     for (int j = 0; j < WN; ++j)
 #pragma unroll
-        for (int h = 0; h < RH; ++h) {
-            const int c = cbase + j * 32 + (PREC == P_F64 ? h * 16 + (lane & 15) : (lane & 31));
+        for (int g = 0; g < 2; ++g) {
             Feat f;
+            const int c = cbase + 32 * j + 16 * g + (lane & 15);
             if (c < od.nc)
                 f = od.cols[c];
             else
                 for (int q = 0; q < MAXH; ++q) f.var[q] = (uint8_t)n;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) coff[j][h][q] = f.var[q] * KTP + soff;
+            for (int q = 0; q < Q; ++q) coff[j][g][q] = f.var[q] * KTP + soff;
         }
 
-    d4 acc64[WM][WN][RH][RH];
-    f16v acc[WM][WN];
-    f16v acc2[WM][WN];  // three-term split: the five small cross products
-    double dacc[WM][WN][16];
-    if constexpr (PREC == P_F64) {
+    d4 acc64[WN][2][2];
+    f4 acc[WN][2][2], acc2[WN][2][2];
+    double dacc[WN][2][2][4];
 #pragma unroll
-        for (int i = 0; i < WM; ++i)
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
-            for (int j = 0; j < WN; ++j)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int h = 0; h < RH; ++h)
+            for (int g = 0; g < 2; ++g)
 #pragma unroll
-                    for (int g = 0; g < RH; ++g) acc64[i][j][h][g] = d4{0.0, 0.0, 0.0, 0.0};
-    } else {
-#pragma unroll
-        for (int i = 0; i < WM; ++i)
-#pragma unroll
-            for (int j = 0; j < WN; ++j)
-#pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    acc[i][j][k] = 0.f;
-                    acc2[i][j][k] = 0.f;
-                    dacc[i][j][k] = 0.0;
+                for (int k = 0; k < 4; ++k) {
+                    acc64[j][h][g][k] = 0.0;
+                    acc[j][h][g][k] = 0.f;
+                    acc2[j][h][g][k] = 0.f;
+                    dacc[j][h][g][k] = 0.0;
                 }
-    }
 
     const int64_t st0 = (int64_t)item.chunk * sd.chunk_stages;
     const int nst = (int)(min(sd.nstages, st0 + sd.chunk_stages) - st0);
@@ -400,200 +395,158 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev &til
     wait_dma();
     __syncthreads();
 
-    int since_flush = 0;
     for (int k = 0; k < nst; ++k) {
         const T *xb = reinterpret_cast<const T *>(lds + (k & 1) * stage_bytes);
-        if (k + 1 < nst) stage_dma(src + (int64_t)(k + 1) * stage_bytes, lds + ((k + 1) & 1) * stage_bytes, stage_bytes, wave, lane);
+        if (k + 1 < nst)
+            stage_dma(src + (int64_t)(k + 1) * stage_bytes, lds + ((k + 1) & 1) * stage_bytes, stage_bytes, wave,
+                      lane);
         if (vmask) {
-            if constexpr (PREC == P_F64) {
 #pragma unroll
-                for (int kk = 0; kk < KT; kk += 8) {
-                    d2 A[WM][2], B[WN][2];
+            for (int kk = 0; kk < KT; kk += STEP) {
+                if constexpr (!BF) {
+                    typedef typename std::conditional<PREC == P_F64, d2, f4>::type V;
+                    V A[2], B[WN][2];
 #pragma unroll
-                    for (int i = 0; i < WM; ++i)
+                    for (int h = 0; h < 2; ++h) {
+                        V v = *reinterpret_cast<const V *>(xb + roff[h][0] + kk);
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            d2 v = *reinterpret_cast<const d2 *>(xb + roff[i][h][0] + kk);
-#pragma unroll
-                            for (int q = 1; q < P; ++q) v *= *reinterpret_cast<const d2 *>(xb + roff[i][h][q] + kk);
-                            A[i][h] = v;
-                        }
+                        for (int q = 1; q < P; ++q) v *= *reinterpret_cast<const V *>(xb + roff[h][q] + kk);
+                        A[h] = v;
+                    }
 #pragma unroll
                     for (int j = 0; j < WN; ++j)
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            d2 v = *reinterpret_cast<const d2 *>(xb + coff[j][h][0] + kk);
+                        for (int g = 0; g < 2; ++g) {
+                            V v = *reinterpret_cast<const V *>(xb + coff[j][g][0] + kk);
 #pragma unroll
-                            for (int q = 1; q < Q; ++q) v *= *reinterpret_cast<const d2 *>(xb + coff[j][h][q] + kk);
-                            B[j][h] = v;
+                            for (int q = 1; q < Q; ++q) v *= *reinterpret_cast<const V *>(xb + coff[j][g][q] + kk);
+                            B[j][g] = v;
                         }
 #pragma unroll
-                    for (int u = 0; u < 2; ++u)
+                    for (int u = 0; u < VEC; ++u)
 #pragma unroll
-                        for (int i = 0; i < WM; ++i)
+                        for (int j = 0; j < WN; ++j)
 #pragma unroll
-                            for (int j = 0; j < WN; ++j)
-                                if (vmask >> (i * WN + j) & 1u) {
+                            for (int h = 0; h < 2; ++h)
 #pragma unroll
-                                    for (int h = 0; h < 2; ++h)
+                                for (int g = 0; g < 2; ++g)
+                                    if (vmask >> (j * 4 + h * 2 + g) & 1u) {
+                                        if constexpr (PREC == P_F64)
+                                            acc64[j][h][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                                A[h][u], B[j][g][u], acc64[j][h][g], 0, 0, 0);
+                                        else
+                                            acc[j][h][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                                A[h][u], B[j][g][u], acc[j][h][g], 0, 0, 0);
+                                    }
+                } else {
+                    bf8 As[2][NS], Bs[WN][2][NS];
 #pragma unroll
-                                        for (int g = 0; g < 2; ++g)
-                                            acc64[i][j][h][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                                A[i][h][u], B[j][g][u], acc64[i][j][h][g], 0, 0, 0);
-                                }
-                }
-            } else if constexpr (PREC == P_F32) {
-#pragma unroll
-                for (int kk = 0; kk < KT; kk += 8) {
-                    f4 A[WM], B[WN];
-#pragma unroll
-                    for (int i = 0; i < WM; ++i) {
-                        f4 v = *reinterpret_cast<const f4 *>(xb + roff[i][0][0] + kk);
-#pragma unroll
-                        for (int q = 1; q < P; ++q) v *= *reinterpret_cast<const f4 *>(xb + roff[i][0][q] + kk);
-                        A[i] = v;
-                    }
-#pragma unroll
-                    for (int j = 0; j < WN; ++j) {
-                        f4 v = *reinterpret_cast<const f4 *>(xb + coff[j][0][0] + kk);
-#pragma unroll
-                        for (int q = 1; q < Q; ++q) v *= *reinterpret_cast<const f4 *>(xb + coff[j][0][q] + kk);
-                        B[j] = v;
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int i = 0; i < WM; ++i)
-#pragma unroll
-                            for (int j = 0; j < WN; ++j)
-                                if (vmask >> (i * WN + j) & 1u)
-                                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i][u], B[j][u], acc[i][j], 0, 0, 0);
-                }
-            } else {
-                constexpr int NS = (PREC == P_BF16X3) ? 3 : 2;
-#pragma unroll 2
-                for (int kk = 0; kk < KT; kk += 16) {
-                    bf8 As[WM][NS], Bs[WN][NS];
-#pragma unroll
-                    for (int i = 0; i < WM; ++i) {
-                        const T *xr = xb + kk;
-                        f4 v0 = *reinterpret_cast<const f4 *>(xr + roff[i][0][0]);
-                        f4 v1 = *reinterpret_cast<const f4 *>(xr + roff[i][0][0] + 4);
+                    for (int h = 0; h < 2; ++h) {
+                        f4 v0 = *reinterpret_cast<const f4 *>(xb + roff[h][0] + kk);
+                        f4 v1 = *reinterpret_cast<const f4 *>(xb + roff[h][0] + kk + 4);
 #pragma unroll
                         for (int q = 1; q < P; ++q) {
-                            v0 *= *reinterpret_cast<const f4 *>(xr + roff[i][0][q]);
-                            v1 *= *reinterpret_cast<const f4 *>(xr + roff[i][0][q] + 4);
+                            v0 *= *reinterpret_cast<const f4 *>(xb + roff[h][q] + kk);
+                            v1 *= *reinterpret_cast<const f4 *>(xb + roff[h][q] + kk + 4);
                         }
                         float v[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
                         if constexpr (NS == 3)
-                            split3(v, As[i][0], As[i][1], As[i][2]);
+                            split3(v, As[h][0], As[h][1], As[h][2]);
                         else
-                            split2(v, As[i][0], As[i][1]);
+                            split2(v, As[h][0], As[h][1]);
                     }
 #pragma unroll
-                    for (int j = 0; j < WN; ++j) {
-                        const T *xr = xb + kk;
-                        f4 v0 = *reinterpret_cast<const f4 *>(xr + coff[j][0][0]);
-                        f4 v1 = *reinterpret_cast<const f4 *>(xr + coff[j][0][0] + 4);
+                    for (int j = 0; j < WN; ++j)
 #pragma unroll
-                        for (int q = 1; q < Q; ++q) {
-                            v0 *= *reinterpret_cast<const f4 *>(xr + coff[j][0][q]);
-                            v1 *= *reinterpret_cast<const f4 *>(xr + coff[j][0][q] + 4);
+                        for (int g = 0; g < 2; ++g) {
+                            f4 v0 = *reinterpret_cast<const f4 *>(xb + coff[j][g][0] + kk);
+                            f4 v1 = *reinterpret_cast<const f4 *>(xb + coff[j][g][0] + kk + 4);
+#pragma unroll
+                            for (int q = 1; q < Q; ++q) {
+                                v0 *= *reinterpret_cast<const f4 *>(xb + coff[j][g][q] + kk);
+                                v1 *= *reinterpret_cast<const f4 *>(xb + coff[j][g][q] + kk + 4);
+                            }
+                            float v[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+                            if constexpr (NS == 3)
+                                split3(v, Bs[j][g][0], Bs[j][g][1], Bs[j][g][2]);
+                            else
+                                split2(v, Bs[j][g][0], Bs[j][g][1]);
                         }
-                        float v[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
-                        if constexpr (NS == 3)
-                            split3(v, Bs[j][0], Bs[j][1], Bs[j][2]);
-                        else
-                            split2(v, Bs[j][0], Bs[j][1]);
-                    }
                     // cross products of the split terms: all 4 for two terms; for three
                     // terms the 6 of combined weight >= 2^-16 (hh, hm, mh, hl, lh, mm),
-                    // hh in its own accumulator so that the five small products do
-                    // not add roundings at the full magnitude; smallest first
+                    // hh in its own accumulator so that the five small products do not
+                    // add roundings at the full magnitude; smallest first
                     constexpr int NP = (NS == 3) ? 6 : 4;
                     constexpr int PA[4] = {0, 0, 1, 1};        // hh, hl, lh, ll
                     constexpr int PB[4] = {0, 1, 0, 1};
                     constexpr int PA3[6] = {0, 0, 1, 0, 2, 1};  // hh, hm, mh, hl, lh, mm
                     constexpr int PB3[6] = {0, 1, 0, 2, 0, 1};
 #pragma unroll
-                    for (int pr = NP - 1; pr >= 0; --pr) {
+                    for (int pr = NP - 1; pr >= 0; --pr)
 #pragma unroll
-                        for (int i = 0; i < WM; ++i)
+                        for (int j = 0; j < WN; ++j)
 #pragma unroll
-                            for (int j = 0; j < WN; ++j)
-                                if (vmask >> (i * WN + j) & 1u) {
-                                    const int ia = (NS == 3) ? PA3[pr] : PA[pr & 3];
-                                    const int ib = (NS == 3) ? PB3[pr] : PB[pr & 3];
-                                    if (NS == 3 && pr > 0)
-                                        acc2[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(As[i][ia], Bs[j][ib],
-                                                                                             acc2[i][j], 0, 0, 0);
-                                    else
-                                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(As[i][ia], Bs[j][ib],
-                                                                                            acc[i][j], 0, 0, 0);
-                                }
-                    }
+                            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                                for (int g = 0; g < 2; ++g)
+                                    if (vmask >> (j * 4 + h * 2 + g) & 1u) {
+                                        const int ia = (NS == 3) ? PA3[pr] : PA[pr & 3];
+                                        const int ib = (NS == 3) ? PB3[pr] : PB[pr & 3];
+                                        if (NS == 3 && pr > 0)
+                                            acc2[j][h][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                                As[h][ia], Bs[j][g][ib], acc2[j][h][g], 0, 0, 0);
+                                        else
+                                            acc[j][h][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                                As[h][ia], Bs[j][g][ib], acc[j][h][g], 0, 0, 0);
+                                    }
                 }
             }
         }
         wait_dma();
         __syncthreads();
         if constexpr (PREC != P_F64) {
-            if (++since_flush >= PT<PREC>::FLUSH_STAGES || k + 1 == nst) {
-                since_flush = 0;
+            // FP32 sums cover one stage; carry them in FP64
 #pragma unroll
-                for (int i = 0; i < WM; ++i)
+            for (int j = 0; j < WN; ++j)
 #pragma unroll
-                    for (int j = 0; j < WN; ++j)
+                for (int h = 0; h < 2; ++h)
 #pragma unroll
-                        for (int q = 0; q < 16; ++q) {
+                    for (int g = 0; g < 2; ++g)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
                             if constexpr (PREC == P_BF16X3) {
-                                dacc[i][j][q] += (double)acc[i][j][q] + (double)acc2[i][j][q];
-                                acc2[i][j][q] = 0.f;
+                                dacc[j][h][g][q] += (double)acc[j][h][g][q] + (double)acc2[j][h][g][q];
+                                acc2[j][h][g][q] = 0.f;
                             } else {
-                                dacc[i][j][q] += (double)acc[i][j][q];
+                                dacc[j][h][g][q] += (double)acc[j][h][g][q];
                             }
-                            acc[i][j][q] = 0.f;
+                            acc[j][h][g][q] = 0.f;
                         }
-            }
         }
     }
 
     // epilogue: write this chunk's sums at their block-storage offsets
     double *dst = sd.partial + (int64_t)item.chunk * sd.stride + od.out_off;
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            if (!(vmask >> (i * WN + j) & 1u)) continue;
-            if constexpr (PREC == P_F64) {
+        for (int g = 0; g < 2; ++g) {
+            if (!(vmask >> (j * 4 + g) & 5u)) continue;  // neither h = 0 nor h = 1 stored
+            const int c = cbase + 32 * j + 16 * g + (lane & 15);
+            if (c >= od.nc) continue;
+            const Feat fc = od.cols[c];
 #pragma unroll
-                for (int g = 0; g < 2; ++g) {
-                    const int c = cbase + j * 32 + g * 16 + (lane & 15);
-                    if (c >= od.nc) continue;
-                    const Feat fc = od.cols[c];
+            for (int h = 0; h < 2; ++h) {
+                if (!(vmask >> (j * 4 + h * 2 + g) & 1u)) continue;
 #pragma unroll
-                    for (int h = 0; h < 2; ++h)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int r = rbase + i * 32 + h * 16 + 4 * q + (lane >> 4);
-                            if (r >= od.nr) continue;
-                            const Feat fr = od.rows[r];
-                            if (fr.blk <= fc.blk)
-                                dst[fr.addr + fc.addr + od.H[(int64_t)fr.blk * od.nbar + fc.blk]] =
-                                    acc64[i][j][h][g][q];
-                        }
-                }
-            } else {
-                const int c = cbase + j * 32 + (lane & 31);
-                if (c >= od.nc) continue;
-                const Feat fc = od.cols[c];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int r = rbase + i * 32 + (q >> 2) * 8 + (lane >> 5) * 4 + (q & 3);
-                    if (r >= od.nr) continue;
+                for (int q = 0; q < 4; ++q) {
+                    // 16 x 16 accumulator layouts: FP64 rows 4q + lane/16, FP32 rows 4*(lane/16) + q
+                    const int r = rbase + 16 * h + (PREC == P_F64 ? 4 * q + (lane >> 4) : 4 * (lane >> 4) + q);
                     const Feat fr = od.rows[r];
-                    if (fr.blk <= fc.blk)
-                        dst[fr.addr + fc.addr + od.H[(int64_t)fr.blk * od.nbar + fc.blk]] = dacc[i][j][q];
+                    if (fr.blk <= fc.blk) {
+                        const double val = (PREC == P_F64) ? acc64[j][h][g][q] : dacc[j][h][g][q];
+                        dst[fr.addr + fc.addr + od.H[(int64_t)fr.blk * od.nbar + fc.blk]] = val;
+                    }
                 }
             }
         }
@@ -602,53 +555,53 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev &til
 // DMAX: the largest order the launch holds (4, 6 or 8).  Only the prefix /
 // suffix lengths up to it are compiled in, so a launch of low orders gets
 // the register allocation of its own bodies.
-template <int PREC, int WM, int WN, int DMAX>
+template <int PREC, int WN, int DMAX>
 __global__ __launch_bounds__(256, 2) void moment_kernel(MomentArgs a) {
     extern __shared__ __align__(16) char lds[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
         const Item item = a.items[it];
         if (item.tile < 0) continue;
-        const TileDev tile = a.tiles[item.tile];
-        const OrderDev od = a.ords[tile.ord];
+        const TileDev *tile = a.tiles + item.tile;
+        const OrderDev od = a.ords[tile->ord];
         const SetDev sd = a.sets ? a.sets[item.set] : a.set0;
         switch (od.p * 8 + od.q) {
-            case 1 * 8 + 1: moment_item<PREC, WM, WN, 1, 1>(item, tile, od, sd, lds, a.n, wave); break;
-            case 1 * 8 + 2: moment_item<PREC, WM, WN, 1, 2>(item, tile, od, sd, lds, a.n, wave); break;
-            case 2 * 8 + 2: moment_item<PREC, WM, WN, 2, 2>(item, tile, od, sd, lds, a.n, wave); break;
+            case 1 * 8 + 1: moment_item<PREC, WN, 1, 1>(item, tile, od, sd, lds, a.n, wave); break;
+            case 1 * 8 + 2: moment_item<PREC, WN, 1, 2>(item, tile, od, sd, lds, a.n, wave); break;
+            case 2 * 8 + 2: moment_item<PREC, WN, 2, 2>(item, tile, od, sd, lds, a.n, wave); break;
             case 2 * 8 + 3:
-                if constexpr (DMAX >= 5) moment_item<PREC, WM, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave);
+                if constexpr (DMAX >= 5) moment_item<PREC, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave);
                 break;
             case 3 * 8 + 3:
-                if constexpr (DMAX >= 6) moment_item<PREC, WM, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave);
+                if constexpr (DMAX >= 6) moment_item<PREC, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave);
                 break;
             case 3 * 8 + 4:
-                if constexpr (DMAX >= 7) moment_item<PREC, WM, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave);
+                if constexpr (DMAX >= 7) moment_item<PREC, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave);
                 break;
             case 4 * 8 + 4:
-                if constexpr (DMAX >= 8) moment_item<PREC, WM, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave);
+                if constexpr (DMAX >= 8) moment_item<PREC, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave);
                 break;
             default: break;
         }
     }
 }
 
-template <int PREC, int WM, int WN>
+template <int PREC, int WN>
 static void launch_moment_dmax(int dmax, const MomentArgs &a, int grid, int lds, hipStream_t s) {
     if (dmax <= 4)
-        hipLaunchKernelGGL((moment_kernel<PREC, WM, WN, 4>), dim3(grid), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((moment_kernel<PREC, WN, 4>), dim3(grid), dim3(256), lds, s, a);
     else if (dmax <= 6)
-        hipLaunchKernelGGL((moment_kernel<PREC, WM, WN, 6>), dim3(grid), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((moment_kernel<PREC, WN, 6>), dim3(grid), dim3(256), lds, s, a);
     else
-        hipLaunchKernelGGL((moment_kernel<PREC, WM, WN, 8>), dim3(grid), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((moment_kernel<PREC, WN, 8>), dim3(grid), dim3(256), lds, s, a);
 }
 
 template <int PREC>
 static hipError_t launch_moment_prec(int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s) {
     const int lds = lds_bytes_moment(PREC, a.n);
     switch (shape) {
-        case TS_1x1: launch_moment_dmax<PREC, 1, 1>(dmax, a, grid, lds, s); break;
-        case TS_2x1: launch_moment_dmax<PREC, 2, 1>(dmax, a, grid, lds, s); break;
+        case TS_1x1: launch_moment_dmax<PREC, 1>(dmax, a, grid, lds, s); break;
+        case TS_1x2: launch_moment_dmax<PREC, 2>(dmax, a, grid, lds, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

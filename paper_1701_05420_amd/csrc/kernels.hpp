@@ -30,8 +30,8 @@ struct RedArgs {
     SetRed set0;
 };
 
-// Work-group tile shapes: WM x WN blocks of 32 x 32 per wave, 2 x 2 waves.
-enum TileShape { TS_1x1 = 0, TS_2x1 = 2 };
+// Wave task shapes: one 32-row block by WN 32-column blocks.
+enum TileShape { TS_1x1 = 0, TS_1x2 = 2 };
 
 int lds_bytes_moment(int prec, int n);
 // row-major data (FP64 with ldx, or FP32 with ldx) -> staged layout, optionally centred

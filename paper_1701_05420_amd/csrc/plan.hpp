@@ -39,20 +39,29 @@ static_assert(sizeof(Feat) == 16, "Feat layout");
 struct OrderDev {
     const Feat *rows;
     const Feat *cols;
-    const int32_t *rb_vmin;  // per 32-row block: smallest v of its real rows
-    const int32_t *cb_wmax;  // per 32-col block: largest w of its real columns
+    const int32_t *rv16;     // per 16-row block: smallest v of its real rows
+    const int32_t *cw16;     // per 16-col block: largest w of its real columns
     const int64_t *H;        // nbar x nbar: (v, w) term of the rank, times b^d
     int64_t out_off;         // offset of this order in the per-chunk partial vector
     int64_t elems;           // stored entries of this order
     int32_t d, p, q, nbar, b, nr, nc, pad;
 };
 
-// A work-group tile of one order's contraction.
+// One wave's share of a work item: rows r0..r0+31 by WN column blocks of 32
+// starting at c0; bit j of mask: column block j holds a stored entry.
+struct WaveTask {
+    int32_t r0;
+    int32_t c0;
+    int32_t mask;
+    int32_t pad;
+};
+
+// A work-group tile: up to four wave tasks of one order.
 struct TileDev {
     int32_t ord;   // index into the OrderDev array
-    int32_t row0;
-    int32_t col0;
-    int32_t pad;
+    int32_t ntask;
+    int32_t pad0, pad1;
+    WaveTask task[4];
 };
 
 // One unit of the moment launch: a tile over one sample chunk of one dataset.

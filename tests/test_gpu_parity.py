@@ -203,7 +203,7 @@ def test_autotune_and_tuned_configs(dev, orc):
     offs_idx = {d: stored_sample(orc, 24, d, 4, 200, seed=d) for d in range(2, 6)}
     want = {d: orc.cumulant_at(Xc, offs_idx[d][1]) for d in offs_idx}
     for prec in PRECS:
-        for shape in ["64x64", "128x64"]:
+        for shape in ["32x32", "32x64"]:
             for target in [256, 1024, 4096]:
                 say(f"tuned prec={prec} shape={shape} target={target}")
                 pc.set_tuning(30_000, 24, 5, 4, prec, shape, target)
