@@ -533,10 +533,22 @@ static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int sha
     if (nch >= 8) nch = (nch + 7) / 8 * 8;
     c->chunk_stages = (c->nstages + nch - 1) / nch;
     c->nchunks = (c->nstages + c->chunk_stages - 1) / c->chunk_stages;
-    // items: chunk ch is processed on XCD (ch % 8); WG i runs on XCD (i % 8)
+    // items: work-group i runs on XCD i % 8.  All items of one chunk share
+    // its stages, so a chunk goes to one XCD (8 or more chunks) or to a
+    // group of 8 / nchunks XCDs; otherwise tiles go round-robin.
     std::vector<std::vector<Item>> per_xcd(8);
-    for (int64_t ch = 0; ch < c->nchunks; ++ch)
-        for (int64_t ti = 0; ti < ntiles; ++ti) per_xcd[ch % 8].push_back({(int32_t)ti, (int32_t)ch, 0, 0});
+    const int64_t nck = c->nchunks;
+    for (int64_t ch = 0; ch < nck; ++ch)
+        for (int64_t ti = 0; ti < ntiles; ++ti) {
+            int x;
+            if (nck >= 8)
+                x = (int)(ch % 8);
+            else if (8 % nck == 0)
+                x = (int)(ch * (8 / nck) + ti % (8 / nck));
+            else
+                x = (int)(ti % 8);
+            per_xcd[x].push_back({(int32_t)ti, (int32_t)ch, 0, 0});
+        }
     size_t longest = 0;
     for (auto &v : per_xcd) longest = std::max(longest, v.size());
     std::vector<Item> items;

@@ -67,8 +67,18 @@ __device__ __forceinline__ void colsum_body(const double *X, int64_t t, int n, i
     double s = 0.0, c = 0.0;
     const int64_t r0 = (int64_t)g * rows_per;
     const int64_t r1 = min(t, r0 + rows_per);
-    if (rl < R)
-        for (int64_t r = r0 + rl; r < r1; r += R) neumaier(s, c, X[r * ldx + col]);
+    if (rl < R) {
+        int64_t r = r0 + rl;
+        // eight independent loads in flight, added in row order
+        for (; r + 7 * R < r1; r += 8 * R) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = X[(r + u * R) * ldx + col];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) neumaier(s, c, x[u]);
+        }
+        for (; r < r1; r += R) neumaier(s, c, X[r * ldx + col]);
+    }
     ss[tid] = s;
     cs[tid] = c;
     __syncthreads();
@@ -89,7 +99,7 @@ __global__ __launch_bounds__(256) void colsum_kernel(const double *X, int64_t t,
 }
 
 // One work-group per column: thread k sums groups k, k+256, ...; the 256
-// compensated partials are then combined in thread order.
+// compensated partials are then combined pairwise in a fixed tree.
 __device__ __forceinline__ void mean_body(const double *part, int groups, int n, int64_t t, double *mean, int i) {
     __shared__ double ss[256], cs[256];
     const int tid = threadIdx.x;
@@ -100,15 +110,17 @@ __device__ __forceinline__ void mean_body(const double *part, int groups, int n,
     }
     ss[tid] = S;
     cs[tid] = C;
-    __syncthreads();
-    if (tid == 0) {
-        double S2 = 0.0, C2 = 0.0;
-        for (int k = 0; k < 256; ++k) {
-            neumaier(S2, C2, ss[k]);
-            neumaier(S2, C2, cs[k]);
+    for (int w = 128; w > 0; w >>= 1) {
+        __syncthreads();
+        if (tid < w) {
+            double S2 = ss[tid], C2 = cs[tid];
+            neumaier(S2, C2, ss[tid + w]);
+            neumaier(S2, C2, cs[tid + w]);
+            ss[tid] = S2;
+            cs[tid] = C2;
         }
-        mean[i] = (S2 + C2) / (double)t;
     }
+    if (tid == 0) mean[i] = (ss[0] + cs[0]) / (double)t;
 }
 
 __global__ __launch_bounds__(256) void mean_kernel(const double *part, int groups, int n, int64_t t,
@@ -258,12 +270,12 @@ struct PT;
 template <>
 struct PT<P_F64> {
     typedef double T;
-    enum { KT = 32, KTP = 36, FLUSH_STAGES = 0 };
+    enum { KT = 32, KTP = 40, FLUSH_STAGES = 0 };
 };
 template <>
 struct PT<P_F32> {
     typedef float T;
-    enum { KT = 64, KTP = 68, FLUSH_STAGES = 1 };
+    enum { KT = 64, KTP = 80, FLUSH_STAGES = 1 };
 };
 template <>
 struct PT<P_BF16X2> {
@@ -277,6 +289,10 @@ struct PT<P_BF16X3> {
 };
 
 int lds_bytes_moment(int prec, int n) { return 2 * (n + 1) * stage_pitch(prec) * stage_esize(prec); }
+static_assert(PT<P_F64>::KTP == stage_pitch(P_F64) && PT<P_F32>::KTP == stage_pitch(P_F32) &&
+                  PT<P_BF16X2>::KTP == stage_pitch(P_BF16X2) && PT<P_F64>::KT == stage_kt(P_F64) &&
+                  PT<P_F32>::KT == stage_kt(P_F32) && PT<P_BF16X2>::KT == stage_kt(P_BF16X2),
+              "stage constants");
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -346,6 +362,9 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                         if (od.rv16[(rbase >> 4) + h] <= od.cw16[((cbase + 32 * j) >> 4) + g])
                             vmask |= 1u << (j * 4 + h * 2 + g);
     }
+    // the mask is the same in every lane; say so, so that the per-sub-block
+    // tests below are scalar branches and not exec-mask regions
+    vmask = __builtin_amdgcn_readfirstlane(vmask);
 
     // LDS offsets (in T) of this lane's operand variables, plus its sample offset
     int roff[2][P], coff[WN][2][Q];
@@ -400,7 +419,10 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
         if (k + 1 < nst)
             stage_dma(src + (int64_t)(k + 1) * stage_bytes, lds + ((k + 1) & 1) * stage_bytes, stage_bytes, wave,
                       lane);
-        if (vmask) {
+        // one stage of products; `all` (a compile-time flag) drops the per-sub-block
+        // tests when every sub-block of the task holds stored entries
+        auto stage = [&](auto all_t) {
+            constexpr bool all = decltype(all_t)::value;
 #pragma unroll
             for (int kk = 0; kk < KT; kk += STEP) {
                 if constexpr (!BF) {
@@ -430,7 +452,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                             for (int h = 0; h < 2; ++h)
 #pragma unroll
                                 for (int g = 0; g < 2; ++g)
-                                    if (vmask >> (j * 4 + h * 2 + g) & 1u) {
+                                    if (all || (vmask >> (j * 4 + h * 2 + g) & 1u)) {
                                         if constexpr (PREC == P_F64)
                                             acc64[j][h][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(
                                                 A[h][u], B[j][g][u], acc64[j][h][g], 0, 0, 0);
@@ -489,7 +511,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                             for (int h = 0; h < 2; ++h)
 #pragma unroll
                                 for (int g = 0; g < 2; ++g)
-                                    if (vmask >> (j * 4 + h * 2 + g) & 1u) {
+                                    if (all || (vmask >> (j * 4 + h * 2 + g) & 1u)) {
                                         const int ia = (NS == 3) ? PA3[pr] : PA[pr & 3];
                                         const int ib = (NS == 3) ? PB3[pr] : PB[pr & 3];
                                         if (NS == 3 && pr > 0)
@@ -501,6 +523,19 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                                     }
                 }
             }
+                };
+        // The three-term BF16 path is bound by its operand arithmetic, not by
+        // the matrix unit, and runs one branch-free copy (computing, and then
+        // not storing, the sub-blocks without stored entries) to keep its
+        // registers down; the others have a test-free copy for full tasks and
+        // a tested one for tasks on the edge of the stored region.
+        if constexpr (PREC == P_BF16X3) {
+            if (vmask) stage(std::true_type());
+        } else {
+            if (vmask == (1u << (4 * WN)) - 1u)
+                stage(std::true_type());
+            else if (vmask)
+                stage(std::false_type());
         }
         wait_dma();
         __syncthreads();
@@ -555,8 +590,16 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
 // DMAX: the largest order the launch holds (4, 6 or 8).  Only the prefix /
 // suffix lengths up to it are compiled in, so a launch of low orders gets
 // the register allocation of its own bodies.
+// Waves per SIMD the register allocation must allow (256 threads = one wave
+// per SIMD per work-group): more resident waves hide the LDS latency between
+// the matrix instructions of any one wave.
 template <int PREC, int WN, int DMAX>
-__global__ __launch_bounds__(256, 2) void moment_kernel(MomentArgs a) {
+constexpr int moment_occupancy() {
+    return WN == 2 ? 2 : (PREC == P_F64 ? 4 : (PREC == P_F32 ? (DMAX <= 4 ? 4 : 3) : (PREC == P_BF16X2 ? 3 : 2)));
+}
+
+template <int PREC, int WN, int DMAX>
+__global__ __launch_bounds__(256, (moment_occupancy<PREC, WN, DMAX>())) void moment_kernel(MomentArgs a) {
     extern __shared__ __align__(16) char lds[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
@@ -663,7 +706,16 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
             const int64_t e = B * be + o;
             const double *pp = partial + ro.out_off + e;
             double S = 0.0;
-            for (int64_t c = 0; c < nchunks; ++c) S += pp[c * stride];
+            int64_t c = 0;
+            // eight independent loads in flight, summed in chunk order
+            for (; c + 8 <= nchunks; c += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = pp[(c + u) * stride];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) S += v[u];
+            }
+            for (; c < nchunks; ++c) S += pp[c * stride];
             const double M = S / tt;
             double res = M;
             if (rec) {

@@ -78,8 +78,13 @@ struct Item {
 // s*KT .. s*KT+KT-1 contiguously, followed by KTP - KT zeros:
 //   Xst[(s * (n + 1) + v) * KTP + k],
 // samples beyond t are zero.  One stage is one contiguous block of memory.
+// The pitch is chosen for the LDS reads of the contraction: lanes in four
+// groups of 16 read 16 bytes at (pitch * v + group * VEC) for a handful of
+// variables v; a pitch of 16 (mod 32) 32-bit words (FP32, FP64) or 4 (mod 32)
+// words (BF16 paths, two reads 32 bytes apart) spreads those reads over
+// distinct banks.
 constexpr int stage_kt(int prec) { return prec == 0 ? 32 : 64; }
-constexpr int stage_pitch(int prec) { return prec == 0 ? 36 : 68; }
+constexpr int stage_pitch(int prec) { return prec == 0 ? 40 : (prec == 1 ? 80 : 68); }
 constexpr int stage_esize(int prec) { return prec == 0 ? 8 : 4; }
 
 // Per dataset: the staged centred data and its partial sums.
