@@ -189,8 +189,10 @@ struct OrderPlan {
     std::vector<uint8_t> tuples;
     std::vector<uint16_t> parts;  // npart x MAXPARTS
     int npart = 0;
+    std::vector<int32_t> loff;  // 2^d LDS offsets of staged sub-blocks (-1: not staged)
+    int lds_elems = 0;          // 0: the recursion reads lower orders from memory
     bool uploaded = false;
-    DevBuf rows_d, cols_d, rbv_d, cbw_d, H_d, tuples_d, parts_d;
+    DevBuf rows_d, cols_d, rbv_d, cbw_d, H_d, tuples_d, parts_d, loff_d;
 };
 
 static cum_status build_order(int n, int b, int d, OrderPlan &o) {
@@ -301,6 +303,17 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
     o.npart = (int)parts.size();
     for (const auto &pm : parts)
         for (int k = 0; k < MAXPARTS; ++k) o.parts.push_back(k < (int)pm.size() ? pm[k] : 0);
+    // the recursion of a block reads, for every set S of 2..d-2 positions,
+    // the lower-order block j_S: stage them all in LDS when they fit
+    o.loff.assign((size_t)1 << d, -1);
+    int64_t lds = 0;
+    for (int mask = 0; mask < (1 << d); ++mask) {
+        const int m = __builtin_popcount(mask);
+        if (d < 4 || m < 2 || m > d - 2) continue;
+        o.loff[mask] = (int32_t)lds;
+        lds += ipow64(b, m);
+    }
+    o.lds_elems = (d >= 4 && lds <= RED_LDS_MAX) ? (int)lds : 0;
 
     return CUM_OK;
 }
@@ -310,7 +323,7 @@ static cum_status upload_order(OrderPlan &o) {
     cum_status st;
     if ((st = upload(o.rows_d, o.rows)) || (st = upload(o.cols_d, o.cols)) || (st = upload(o.rbv_d, o.rv16)) ||
         (st = upload(o.cbw_d, o.cw16)) || (st = upload(o.H_d, o.H)) || (st = upload(o.tuples_d, o.tuples)) ||
-        (st = upload(o.parts_d, o.parts)))
+        (st = upload(o.parts_d, o.parts)) || (st = upload(o.loff_d, o.loff)))
         return st;
     o.uploaded = true;
     return CUM_OK;
@@ -411,6 +424,7 @@ static cum_status upload_call(CallPlan &c) {
         c.ods[i].H = (const int64_t *)o->H_d.p;
         c.red[i].tuples = (const uint8_t *)o->tuples_d.p;
         c.red[i].parts = (const uint16_t *)o->parts_d.p;
+        c.red[i].loff = o->lds_elems ? (const int32_t *)o->loff_d.p : nullptr;
     }
     if ((st = upload(c.ords_d, c.ods)) || (st = upload(c.tiles_d, c.tdev)) || (st = upload(c.items_d, c.items)) ||
         (st = upload(c.red_d, c.red)))
@@ -510,8 +524,11 @@ static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int sha
         c->ods.push_back(od);
         order_tiles(*o, wn, d - dlo, tiles);
         RedOrder ro;
+        memset(&ro, 0, sizeof ro);
         ro.tuples = nullptr;
         ro.parts = nullptr;
+        ro.loff = nullptr;
+        ro.lds_elems = o->lds_elems;
         ro.nblocks = o->nblocks;
         ro.out_off = off;
         ro.d = d;
@@ -643,13 +660,15 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
             ra.nords = 1;
             ra.nbtot = ra.nb0;
         }
-        HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(ra, 1, s); }));
+        int lds = recursion ? c->red[i0].lds_elems : 0;
+        if (recursion && ra.nords == 2) lds = std::max(lds, c->red[i0 + 1].lds_elems);
+        HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(ra, 1, lds, s); }));
         if (!recursion) {
             for (int dd = d + 1; dd <= c->dhi; ++dd) {
                 RedArgs rb = ra;
                 rb.ords = red_d + (dd - c->dlo);
                 rb.nb0 = rb.nbtot = c->red[dd - c->dlo].nblocks;
-                HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(rb, 1, s); }));
+                HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(rb, 1, 0, s); }));
             }
             break;
         }
@@ -1166,7 +1185,9 @@ static cum_status batch_enqueue(cum_batch &p, hipStream_t s) {
         ra.nb0 = p.red[i0].nblocks;
         ra.nbtot = ra.nb0 + (ra.nords == 2 ? p.red[i0 + 1].nblocks : 0);
         ra.sets = (const SetRed *)p.setred_d.p;
-        HIP_TRY(launch_reduce(ra, p.nsets, s));
+        int lds = p.red[i0].lds_elems;
+        if (ra.nords == 2) lds = std::max(lds, p.red[i0 + 1].lds_elems);
+        HIP_TRY(launch_reduce(ra, p.nsets, lds, s));
     }
     return CUM_OK;
 }
@@ -1213,8 +1234,11 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
         od.pad = 0;
         p->ods.push_back(od);
         RedOrder ro;
+        memset(&ro, 0, sizeof ro);
         ro.tuples = (const uint8_t *)o->tuples_d.p;
         ro.parts = (const uint16_t *)o->parts_d.p;
+        ro.loff = o->lds_elems ? (const int32_t *)o->loff_d.p : nullptr;
+        ro.lds_elems = o->lds_elems;
         ro.nblocks = o->nblocks;
         ro.out_off = off;
         ro.d = d;

@@ -672,6 +672,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
     __shared__ int64_t base[1 << MAXD];
     __shared__ int tup[MAXD];
     __shared__ double *kap[MAXD - 1];
+    extern __shared__ double sub[];  // staged lower-order sub-blocks of the current block
     const int tid = threadIdx.x;
     const SetRed sr = a.sets ? a.sets[blockIdx.y] : a.set0;
 #pragma unroll
@@ -686,21 +687,35 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
         const RedOrder ro = a.ords[oi];
         const int d = ro.d, b = ro.b;
         const int64_t be = ipow_dev(b, d);
+        const bool rec = a.recursion && d >= 4;
+        const bool staged = rec && ro.loff != nullptr;
         __syncthreads();
         if (tid < d) tup[tid] = ro.tuples[B * d + tid];
         __syncthreads();
-        const bool rec = a.recursion && d >= 4;
         if (rec) {
             for (int mask = tid; mask < (1 << d); mask += 256) {
                 const int m = __popc(mask);
                 if (m < 2 || m > d - 2) continue;
                 int u[MAXD], mm = 0;
-                for (int k = 0; k < d; ++k)
-                    if (mask >> k & 1) u[mm++] = tup[k];
+#pragma unroll
+                for (int k = 0; k < MAXD; ++k)
+                    if (k < d && (mask >> k & 1)) u[mm++] = tup[k];
                 base[mask] = rank_sorted(u, m, ro.nbar) * ipow_dev(b, m);
             }
         }
         __syncthreads();
+        if (staged) {
+            // the block's sub-blocks j_S of every position set S, into LDS
+            for (int mask = 0; mask < (1 << d); ++mask) {
+                const int off = ro.loff[mask];
+                if (off < 0) continue;
+                const int m = __popc(mask);
+                const int sz = (int)ipow_dev(b, m);
+                const double *srcp = kap[m - 2] + base[mask];
+                for (int e = tid; e < sz; e += 256) sub[off + e] = srcp[e];
+            }
+            __syncthreads();
+        }
         double *out = kap[d - 2];
         for (int64_t o = tid; o < be; o += 256) {
             const int64_t e = B * be + o;
@@ -719,22 +734,26 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
             const double M = S / tt;
             double res = M;
             if (rec) {
-                int r[MAXD];
+                int r[MAXD];  // in-block digits, first position most significant
                 int64_t oo = o;
-                for (int k = d - 1; k >= 0; --k) {
-                    r[k] = (int)(oo % b);
-                    oo /= b;
-                }
+#pragma unroll
+                for (int k = MAXD - 1; k >= 0; --k)
+                    if (k < d) {
+                        r[k] = (int)(oo % b);
+                        oo /= b;
+                    }
                 double sum = 0.0;
                 for (int z = 0; z < ro.npart; ++z) {
                     double prod = 1.0;
+#pragma unroll
                     for (int pt = 0; pt < MAXPARTS; ++pt) {
                         const int mask = ro.parts[z * MAXPARTS + pt];
                         if (!mask) break;
-                        int64_t flat = 0;
-                        for (int k = 0; k < d; ++k)
-                            if (mask >> k & 1) flat = flat * b + r[k];
-                        prod *= kap[__popc(mask) - 2][base[mask] + flat];
+                        int flat = 0;
+#pragma unroll
+                        for (int k = 0; k < MAXD; ++k)
+                            if (k < d && (mask >> k & 1)) flat = flat * b + r[k];
+                        prod *= staged ? sub[ro.loff[mask] + flat] : kap[__popc(mask) - 2][base[mask] + flat];
                     }
                     sum += prod;
                 }
@@ -746,10 +765,10 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
     }
 }
 
-hipError_t launch_reduce(const RedArgs &a, int nsets, hipStream_t s) {
+hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_doubles, hipStream_t s) {
     int64_t gx = a.nbtot;
     if (gx > 65535) gx = 65535;
-    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)gx, (unsigned)nsets), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)gx, (unsigned)nsets), dim3(256), (size_t)lds_doubles * 8, s, a);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ int lds_bytes_moment(int prec, int n);
 hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xst, int prec,
                         bool center, bool in_f64, hipStream_t s);
 hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s);
-hipError_t launch_reduce(const RedArgs &a, int nsets, hipStream_t s);
+hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_doubles, hipStream_t s);
 hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,
                          hipStream_t s);
 hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s);

@@ -102,10 +102,15 @@ constexpr int MAXPARTS = MAXD / 2;  // parts of size >= 2 in a partition of <= M
 struct RedOrder {
     const uint8_t *tuples;  // nblocks x d sorted block tuples (lexicographic order)
     const uint16_t *parts;  // npart x MAXPARTS position masks (0 = unused)
+    const int32_t *loff;    // 2^d: LDS offset of the staged sub-block of each position
+                            // mask of 2..d-2 positions (null: read them from memory)
     int64_t nblocks;
     int64_t out_off;        // offset of this order in the per-chunk partial vector
     int32_t d, npart, nbar, b;
+    int32_t lds_elems;      // doubles staged per block (0 without staging)
+    int32_t pad;
 };
+constexpr int RED_LDS_MAX = 6144;  // doubles of lower-order sub-blocks staged per block (48 KiB)
 
 struct SetRed {
     const double *partial;
