@@ -350,8 +350,8 @@ static cum_status get_order(int n, int b, int d, OrderPlan **out) {
 // Work-group tiles of one order.  A wave task is a 32-row block by WN
 // consecutive 32-column blocks holding at least one stored entry; its cost
 // is the number of stored 16 x 16 sub-blocks.  Tasks are sorted by cost and
-// packed four to a work-group, so the four waves of a work-group have
-// nearly equal work and no wave sits idle except in the order's last tile.
+// packed WG_WAVES to a work-group, so the waves of a work-group have nearly
+// equal work and no wave sits idle except in the order's last tile.
 struct HostTile {
     TileDev t;
     int cost;  // the largest task cost of the tile
@@ -377,12 +377,12 @@ static void order_tiles(const OrderPlan &o, int wn, int ord_index, std::vector<H
             if (mask) tasks.push_back({{rb * 32, cb * 32, mask, 0}, cost});
         }
     std::stable_sort(tasks.begin(), tasks.end(), [](const Task &x, const Task &y) { return x.cost > y.cost; });
-    for (size_t i = 0; i < tasks.size(); i += 4) {
+    for (size_t i = 0; i < tasks.size(); i += WG_WAVES) {
         HostTile ht;
         memset(&ht.t, 0, sizeof ht.t);
         ht.t.ord = ord_index;
         ht.cost = 0;
-        for (size_t k = i; k < std::min(tasks.size(), i + 4); ++k) {
+        for (size_t k = i; k < std::min(tasks.size(), i + (size_t)WG_WAVES); ++k) {
             ht.t.task[ht.t.ntask++] = tasks[k].w;
             ht.cost = std::max(ht.cost, tasks[k].cost);
         }

@@ -251,7 +251,7 @@ hipError_t launch_batch_stamp(unsigned long long *stamps, int nsets, hipStream_t
 // ---------------------------------------------------------------------------
 // Block moment contraction.
 //
-// A work item is one work-group of four wave tasks (each a 32-row block by
+// A work item is one work-group of WG_WAVES wave tasks (each a 32-row block by
 // WN 32-column blocks of one order's (prefix rows) x (suffix columns)
 // product, packed on the host so that no wave is idle) over one chunk of
 // stages of one dataset.  Each stage is copied from HBM to
@@ -299,7 +299,7 @@ typedef __attribute__((address_space(3))) void lds_void;
 // Copy one stage (bytes, a multiple of 16) from global to LDS with the DMA
 // path: each wave moves 1 KiB per instruction, lane l its 16-byte piece.
 __device__ __forceinline__ void stage_dma(const char *src, char *lds, int bytes, int wave, int lane) {
-    for (int c = wave * 1024; c < bytes; c += 4 * 1024) {
+    for (int c = wave * 1024; c < bytes; c += WG_WAVES * 1024) {
         const int off = c + lane * 16;
         if (off < bytes)
             __builtin_amdgcn_global_load_lds((const void *)(src + off), (lds_void *)(lds + c), 16, 0, 0);
@@ -590,16 +590,19 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
 // DMAX: the largest order the launch holds (4, 6 or 8).  Only the prefix /
 // suffix lengths up to it are compiled in, so a launch of low orders gets
 // the register allocation of its own bodies.
-// Waves per SIMD the register allocation must allow (256 threads = one wave
-// per SIMD per work-group): more resident waves hide the LDS latency between
-// the matrix instructions of any one wave.
+// Waves per SIMD the register allocation must allow: more resident waves
+// hide the LDS latency between the matrix instructions of any one wave.  A
+// work-group puts WG_WAVES / 4 waves on each SIMD, so the count is rounded
+// down to a multiple of that.
 template <int PREC, int WN, int DMAX>
 constexpr int moment_occupancy() {
-    return WN == 2 ? 2 : (PREC == P_F64 ? 4 : (PREC == P_F32 ? (DMAX <= 4 ? 4 : 3) : (PREC == P_BF16X2 ? 3 : 2)));
+    constexpr int want = WN == 2 ? 2 : (PREC == P_F64 ? 4 : (PREC == P_F32 ? (DMAX <= 4 ? 4 : 3) : (PREC == P_BF16X2 ? 3 : 2)));
+    constexpr int per = WG_WAVES / 4;
+    return want / per * per > 0 ? want / per * per : per;
 }
 
 template <int PREC, int WN, int DMAX>
-__global__ __launch_bounds__(256, (moment_occupancy<PREC, WN, DMAX>())) void moment_kernel(MomentArgs a) {
+__global__ __launch_bounds__(64 * WG_WAVES, (moment_occupancy<PREC, WN, DMAX>())) void moment_kernel(MomentArgs a) {
     extern __shared__ __align__(16) char lds[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
@@ -632,11 +635,11 @@ __global__ __launch_bounds__(256, (moment_occupancy<PREC, WN, DMAX>())) void mom
 template <int PREC, int WN>
 static void launch_moment_dmax(int dmax, const MomentArgs &a, int grid, int lds, hipStream_t s) {
     if (dmax <= 4)
-        hipLaunchKernelGGL((moment_kernel<PREC, WN, 4>), dim3(grid), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((moment_kernel<PREC, WN, 4>), dim3(grid), dim3(64 * WG_WAVES), lds, s, a);
     else if (dmax <= 6)
-        hipLaunchKernelGGL((moment_kernel<PREC, WN, 6>), dim3(grid), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((moment_kernel<PREC, WN, 6>), dim3(grid), dim3(64 * WG_WAVES), lds, s, a);
     else
-        hipLaunchKernelGGL((moment_kernel<PREC, WN, 8>), dim3(grid), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((moment_kernel<PREC, WN, 8>), dim3(grid), dim3(64 * WG_WAVES), lds, s, a);
 }
 
 template <int PREC>

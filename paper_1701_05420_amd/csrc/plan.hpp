@@ -56,12 +56,19 @@ struct WaveTask {
     int32_t pad;
 };
 
-// A work-group tile: up to four wave tasks of one order.
+// Waves per work-group of the contraction: they share one staged copy of
+// the samples in LDS (one DMA per stage for all of them).
+#ifndef CUM_WG_WAVES
+#define CUM_WG_WAVES 4
+#endif
+constexpr int WG_WAVES = CUM_WG_WAVES;
+
+// A work-group tile: up to WG_WAVES wave tasks of one order.
 struct TileDev {
     int32_t ord;   // index into the OrderDev array
     int32_t ntask;
     int32_t pad0, pad1;
-    WaveTask task[4];
+    WaveTask task[WG_WAVES];
 };
 
 // One unit of the moment launch: a tile over one sample chunk of one dataset.
