@@ -90,7 +90,7 @@ typedef struct {
 } cum_layout;
 
 /* Largest supported order. */
-#define CUM_MAX_ORDER 8
+#define CUM_MAX_ORDER 10
 
 /* Host only.  Layout of the order-d block storage for n variables and block
  * size b.  Requires n >= 1, 1 <= b <= n, 1 <= d <= CUM_MAX_ORDER. */

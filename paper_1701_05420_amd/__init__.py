@@ -26,7 +26,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 PRECS = {"f64": 0, "f32": 1, "bf16x2": 2, "bf16x3": 3}
-MAX_ORDER = 8
+MAX_ORDER = 10
 
 EXPORTS = [
     "cum_layout_query", "cum_workspace_size", "cum_center", "cum_moment_blocks", "cum_cumulants", "cum_unfold",

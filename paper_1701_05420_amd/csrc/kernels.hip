@@ -587,7 +587,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
         }
 }
 
-// DMAX: the largest order the launch holds (4, 6 or 8).  Only the prefix /
+// DMAX: the largest order the launch holds (4, 6, 8 or 10).  Only the prefix /
 // suffix lengths up to it are compiled in, so a launch of low orders gets
 // the register allocation of its own bodies.
 // Waves per SIMD the register allocation must allow: more resident waves
@@ -627,6 +627,12 @@ __global__ __launch_bounds__(64 * WG_WAVES, (moment_occupancy<PREC, WN, DMAX>())
             case 4 * 8 + 4:
                 if constexpr (DMAX >= 8) moment_item<PREC, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave);
                 break;
+            case 4 * 8 + 5:
+                if constexpr (DMAX >= 9) moment_item<PREC, WN, 4, 5>(item, tile, od, sd, lds, a.n, wave);
+                break;
+            case 5 * 8 + 5:
+                if constexpr (DMAX >= 10) moment_item<PREC, WN, 5, 5>(item, tile, od, sd, lds, a.n, wave);
+                break;
             default: break;
         }
     }
@@ -638,8 +644,10 @@ static void launch_moment_dmax(int dmax, const MomentArgs &a, int grid, int lds,
         hipLaunchKernelGGL((moment_kernel<PREC, WN, 4>), dim3(grid), dim3(64 * WG_WAVES), lds, s, a);
     else if (dmax <= 6)
         hipLaunchKernelGGL((moment_kernel<PREC, WN, 6>), dim3(grid), dim3(64 * WG_WAVES), lds, s, a);
-    else
+    else if (dmax <= 8)
         hipLaunchKernelGGL((moment_kernel<PREC, WN, 8>), dim3(grid), dim3(64 * WG_WAVES), lds, s, a);
+    else
+        hipLaunchKernelGGL((moment_kernel<PREC, WN, 10>), dim3(grid), dim3(64 * WG_WAVES), lds, s, a);
 }
 
 template <int PREC>

@@ -20,8 +20,8 @@
 
 namespace cum {
 
-constexpr int MAXD = 8;   // largest order
-constexpr int MAXH = 4;   // longest prefix / suffix = ceil(MAXD / 2)
+constexpr int MAXD = 10;  // largest order
+constexpr int MAXH = 5;   // longest prefix / suffix = ceil(MAXD / 2)
 constexpr int MAXN = 112; // variables (index n is the zero row of the staged data)
 constexpr int FEAT_BLOCK = 32;
 
@@ -32,8 +32,9 @@ struct Feat {
     int32_t blk;           // row: last prefix block v (INT32_MAX for padding rows)
                            // col: first suffix block w (-1 for padding columns)
     uint8_t var[MAXH];     // variable of each position (n = the zero column)
+    uint8_t pad[3];
 };
-static_assert(sizeof(Feat) == 16, "Feat layout");
+static_assert(sizeof(Feat) == 24, "Feat layout");
 
 // Everything a kernel needs to know about one order (device pointers).
 struct OrderDev {

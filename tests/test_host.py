@@ -45,7 +45,7 @@ def test_layout_matches_oracle_counts(pc, orc, n, b):
 
 
 def test_layout_rejects_bad_arguments(pc):
-    for args in [(0, 2, 1), (4, 2, 0), (4, 2, 5), (4, 0, 1), (4, 9, 1)]:
+    for args in [(0, 2, 1), (4, 2, 0), (4, 2, 5), (4, 0, 1), (4, 11, 1)]:
         with pytest.raises(pc.CumulantError):
             pc.layout(*args)
 
@@ -68,7 +68,7 @@ def test_stored_offset_against_oracle_positions(pc, orc, n, d, b):
 
 @pytest.mark.parametrize("n,b", [(1, 1), (3, 1), (5, 2), (7, 3), (16, 2), (13, 4), (33, 5)])
 def test_plan_covers_every_stored_entry_once(pc, n, b):
-    for d in range(2, 9):
+    for d in range(2, 11):
         if pc.layout(n, d, b)["elems"] > 3_000_000:
             continue
         pc.plan_check(n, d, b)
@@ -96,7 +96,7 @@ def test_workspace_size_is_host_only_and_monotone(pc):
     with pytest.raises(pc.CumulantError):
         pc.workspace_size(0, 48, 4, 4, "f32")
     with pytest.raises(pc.CumulantError):
-        pc.workspace_size(10, 48, 9, 4, "f32")
+        pc.workspace_size(10, 48, 11, 4, "f32")
 
 
 def _raw(pc, fn, *args):
@@ -112,7 +112,7 @@ def test_entry_points_validate_before_touching_the_device(pc):
     assert _raw(pc, "cum_cumulants", P, 0, 4, 4, 4, 2, 0, N, kap, P, 1 << 30, N) == -1      # t = 0
     assert _raw(pc, "cum_cumulants", P, 10, 4, 3, 4, 2, 0, N, kap, P, 1 << 30, N) == -1     # ldx < n
     assert _raw(pc, "cum_cumulants", P, 10, 4, 4, 4, 5, 0, N, kap, P, 1 << 30, N) == -1     # b > n
-    assert _raw(pc, "cum_cumulants", P, 10, 4, 4, 9, 2, 0, N, kap, P, 1 << 30, N) == -1     # d_max > 8
+    assert _raw(pc, "cum_cumulants", P, 10, 4, 4, 11, 2, 0, N, kap, P, 1 << 30, N) == -1    # d_max > 10
     assert _raw(pc, "cum_cumulants", P, 10, 4, 4, 4, 2, 7, N, kap, P, 1 << 30, N) == -4     # prec
     assert _raw(pc, "cum_cumulants", P, 10, 4, 4, 4, 2, 0, N, kap_null, P, 1 << 30, N) == -1
     assert _raw(pc, "cum_cumulants", N, 10, 4, 4, 4, 2, 0, N, kap, P, 1 << 30, N) == -1
@@ -120,5 +120,5 @@ def test_entry_points_validate_before_touching_the_device(pc):
     assert _raw(pc, "cum_moment_blocks", P, 0, 10, 4, 1, 2, P, P, 1 << 30, N) == -1         # d = 1
     assert _raw(pc, "cum_moment_blocks", P, 0, 10, 4, 4, 2, P, P, 8, N) == -2
     assert _raw(pc, "cum_center", P, 10, 4, 2, 0, P, P, P, 1 << 20, N) == -1                # ldx < n
-    assert _raw(pc, "cum_unfold", P, 4, 9, 2, P, N) == -1
+    assert _raw(pc, "cum_unfold", P, 4, 11, 2, P, N) == -1
     assert b"workspace" in pc._lib.cum_last_error() or True

@@ -68,7 +68,7 @@ def test_F_recurrence_and_sigma_max(orc):
         return len(orc.partitions(d, min_part=1, min_parts=1))
 
     assert [F(d) for d in range(2, 7)] == [1, 1, 4, 11, 41]
-    for d in range(1, 8):
+    for d in range(1, 10):
         assert F(d + 1) == B(d) - F(d)
     for d in range(2, 9):
         P = orc.partitions(d, 2, 2)
@@ -305,3 +305,15 @@ def test_block_counts_and_fold(orc):
     # every sorted multi-index appears at least once (redundant copies in diagonal blocks)
     have = {tuple(sorted(ix)) for ix in idx if ix[0] >= 0}
     assert have == set(itertools.combinations_with_replacement(range(n), d))
+
+
+def test_high_orders_against_raw_moment_route(orc):
+    """Orders 7 and 8 (the paper's method reaches order 10): the FP64 oracle
+    on shifted small-integer data against the Moebius route on raw moments."""
+    X = workloads.dyadic_integers(t=16, n=2, seed=4, lo=-1, hi=1) + np.array([2.0, -1.0])
+    _, K = orc.cumulants_dense(X, 8)
+    Xf = exact.to_fractions(X)
+    for idx in [(0,) * 7, (0, 1, 0, 1, 1, 0, 1), (1,) * 8, (0, 0, 0, 1, 1, 1, 0, 1)]:
+        want = exact.cumulant_moebius(Xf, idx)
+        assert Fraction(float(want)) == want
+        assert K[len(idx)][idx] == float(want), idx
