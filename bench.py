@@ -7,9 +7,12 @@ chunk reduction and the cumulant recursion.  ``value`` is the effective
 throughput of the mixed-precision path,
     algorithmic FLOP = sum_{d=2}^{d_max} 2 * t * stored_d
 (one multiply-add per stored block entry per sample, the work of the block
-method) divided by the measured step time.  The FP64 path and any further
-precisions are timed on the same data and reported beside it, each with its
-per-order relative error against the FP64 CPU oracle on sampled entries.
+method) divided by the measured step time.  The contraction itself may sum
+fewer entries (with inner block size 1, each distinct sorted variable tuple
+once); the roofline of the moment kernel counts the entries it does sum.
+The FP64 path and any further precisions are timed on the same data and
+reported beside it, each with its per-order relative error against the FP64
+CPU oracle on sampled entries.
 
 Prints ONE JSON line.
 """
@@ -226,6 +229,7 @@ def main():
     X = workloads.generate(args.workload)
     Xd = torch.from_numpy(X).cuda()
     flops = alg_flops(pc, t, n, d_max, b)
+    uflops = alg_flops(pc, t, n, d_max, 1)  # each distinct sorted variable tuple once
 
     precs = [args.prec] + [p for p in args.compare.split(",") if p and p != args.prec]
     res, kappa = {}, {}
@@ -234,12 +238,16 @@ def main():
         wall, kinds, out, tuned = time_path(torch, pc, Xd, d_max, b, p, args.steps, args.warmup, not args.no_tune)
         mom_ms, mom_n = kinds["moment"]
         per_launch = mom_ms / max(mom_n, 1)
-        achieved = flops / (per_launch * 1e-3) / 1e12
+        cfg = pc.get_tuning(t, n, d_max, b, p)
+        kflops = alg_flops(pc, t, n, d_max, cfg["inner_b"])  # entries the contraction sums
+        achieved = kflops / (per_launch * 1e-3) / 1e12
         res[p] = {"ms_per_step": wall * 1e3, "tflops": flops / wall / 1e12,
+                  "tflops_unique": uflops / wall / 1e12,
                   "moment_ms_per_launch": per_launch, "moment_tflops": achieved,
+                  "moment_flop_per_launch": kflops,
                   "mfma_frac": achieved * PRODUCTS[p] / PEAK[p],
                   "kernel_ms": {k: v[0] / args.steps for k, v in kinds.items() if v[1]},
-                  "tuning": tuned}
+                  "tuning": tuned, "config": cfg}
         kappa[p] = {d: out[d].cpu().numpy() for d in out}
         log(f"  {p}: {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s; "
             f"moment kernel {per_launch:.3f} ms = {achieved:.2f} TFLOP/s")
@@ -254,6 +262,7 @@ def main():
             "unit": "TFLOP/s", "frac": r["moment_tflops"] * PRODUCTS[main_p] / PEAK[main_p],
             "traffic": traffic_record(main_p, args.workload),
             "kernel": "moment_kernel", "algorithmic_tflops": r["moment_tflops"],
+            "flop_per_launch": r["moment_flop_per_launch"], "inner_b": r["config"]["inner_b"],
             "ms_per_launch": r["moment_ms_per_launch"]}
     line = {
         "metric": METRIC,
@@ -269,7 +278,7 @@ def main():
         "dtype": DTYPE[main_p],
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "b": b, "d_max": d_max, "t": t, "prec": main_p,
-                   "alg_flop_per_step": flops},
+                   "alg_flop_per_step": flops, "unique_flop_per_step": uflops},
         "roofline": roof,
         "paths": {p: {k: v for k, v in res[p].items()} for p in precs},
         "rel_err": {str(d): errs[d] for d in errs},

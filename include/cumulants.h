@@ -146,15 +146,22 @@ cum_status cum_unfold(const double *blocks, int n, int d, int b, double *dense, 
 cum_status cum_stored_offset(int n, int d, int b, const int32_t *idx /* host */, int64_t *offset /* host */);
 
 /* ------------------------------------------------------------------------
- * Autotuning of the contraction's launch shape (the paper picks its block
- * size b by timing, Section 5.2; here b is the caller's storage choice and
- * the tuned knobs are the launch's):
+ * Autotuning of the contraction (the paper picks its block size b by
+ * timing, Section 5.2; here b is the caller's storage choice, and the tuned
+ * knobs are the block size the contraction works in and the launch's):
  *   shape         one wave's task in one order's (rows x columns) product:
  *                 0 = 32 x 32, 2 = 32 x 64 entries (four tasks per
  *                 work-group, packed so that waves have equal work);
  *   target_items  about how many (tile, sample-chunk) work items to create;
  *                 it sets the sample chunk length, hence the split over
- *                 samples and the size of the FP64 partial-sum buffer.
+ *                 samples and the size of the FP64 partial-sum buffer;
+ *   inner_b       1..b: block size of the layout the contraction fills.
+ *                 With inner_b = b every stored entry is summed, redundant
+ *                 copies in diagonal blocks included (as Alg. 1 does); with
+ *                 a smaller inner_b fewer redundant copies are summed (with
+ *                 1, each distinct sorted variable tuple once), and the
+ *                 reduction reads each stored entry's sums at its sorted
+ *                 variable tuple.  Default 1.
  * A tuned choice applies to later calls with the same (t, n, d_max, b, prec)
  * and changes their workspace size: query cum_workspace_size afterwards.
  * With the environment variable CUM_TUNE_FILE set, choices are also read
@@ -163,6 +170,7 @@ cum_status cum_stored_offset(int n, int d, int b, const int32_t *idx /* host */,
 typedef struct {
     int32_t shape;
     int32_t target_items;
+    int32_t inner_b;
     float ms;  /* autotune: measured time of the chosen configuration */
 } cum_tuning;
 
@@ -175,8 +183,13 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
                         void *stream, cum_tuning *best /* host */);
 
 /* Host only.  Set (tune != NULL) or forget (tune == NULL) the configuration
- * used for cum_cumulants(t, n, d_max, b, prec). */
+ * used for cum_cumulants(t, n, d_max, b, prec).  CUM_EINVAL for an unknown
+ * shape, target_items < 1 or inner_b outside 1..b. */
 cum_status cum_set_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, const cum_tuning *tune /* host */);
+
+/* Host only.  The configuration cum_cumulants(t, n, d_max, b, prec) uses:
+ * the tuned one if there is one, else the defaults (ms = 0). */
+cum_status cum_get_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, cum_tuning *tune /* host out */);
 
 /* ------------------------------------------------------------------------
  * Batched cumulants: many datasets of the same width n and uneven sample
@@ -210,8 +223,8 @@ cum_status cum_batch_run(cum_batch *plan, const double *const *X_i, double *cons
 cum_status cum_batch_timestamps(cum_batch *plan, uint64_t *start /* host */, uint64_t *ticks /* host */,
                                 double *hz /* host */);
 
-/* Time the batch's candidate launch configurations (tile shape x work-item
- * target) on the datasets X_i (host array of device pointers) and keep the
+/* Time the batch's candidate configurations (inner block size x tile shape x
+ * work-item target) on the datasets X_i (host array of device pointers) and keep the
  * fastest for this plan (and for later plans of the same shape and count);
  * the graph is captured again on the next run.  Synchronises the device.
  * best (host) may be NULL. */
@@ -220,8 +233,10 @@ cum_status cum_batch_autotune(cum_batch *plan, const double *const *X_i, cum_tun
 cum_status cum_batch_destroy(cum_batch *plan);
 
 /* Host only.  Check that the moment-contraction tiling of order d covers
- * every stored entry exactly once (no GPU needed).  Returns CUM_OK or
- * CUM_EINVAL with a message. */
+ * every stored entry exactly once and multiplies the variables stored there,
+ * and that the rank table the reduction uses to find a sorted tuple's
+ * partial sums gives every tuple's position (no GPU needed).  Returns CUM_OK
+ * or CUM_EINVAL with a message. */
 cum_status cum_plan_check(int n, int d, int b);
 
 /* Host only.  Measurement helpers.  While enabled on the calling thread,

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcumulants.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1701_05420_amd.build` "
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1701_05420_amd/build.py` "
                       "(or __graft_entry__.build()); there is no fallback implementation")
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -31,14 +31,15 @@ MAX_ORDER = 10
 EXPORTS = [
     "cum_layout_query", "cum_workspace_size", "cum_center", "cum_moment_blocks", "cum_cumulants", "cum_unfold",
     "cum_stored_offset", "cum_batch_create", "cum_batch_run", "cum_batch_timestamps", "cum_batch_destroy",
-    "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning",
+    "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning", "cum_get_tuning",
     "cum_batch_autotune", "cum_status_str", "cum_last_error",
 ]
 SHAPES = {"32x32": 0, "32x64": 2}
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("shape", ctypes.c_int32), ("target_items", ctypes.c_int32), ("ms", ctypes.c_float)]
+    _fields_ = [("shape", ctypes.c_int32), ("target_items", ctypes.c_int32), ("inner_b", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
 KINDS = ["center", "moment", "reduce", "unfold", "batch"]
 
 
@@ -65,6 +66,7 @@ _lib.cum_plan_check.argtypes = [_I, _I, _I]
 _lib.cum_timing_enable.argtypes = [_I]
 _lib.cum_autotune.argtypes = [_VP, _I64, _I, _I64, _I, _I, _I, _VP, ctypes.POINTER(Tuning)]
 _lib.cum_set_tuning.argtypes = [_I64, _I, _I, _I, _I, ctypes.POINTER(Tuning)]
+_lib.cum_get_tuning.argtypes = [_I64, _I, _I, _I, _I, ctypes.POINTER(Tuning)]
 _lib.cum_batch_autotune.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(Tuning)]
 _lib.cum_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]
 _lib.cum_status_str.argtypes = [_I]
@@ -126,15 +128,22 @@ def autotune(X, d_max: int, b: int, prec="f32", stream=None) -> dict:
     out = Tuning()
     _check(_lib.cum_autotune(X.data_ptr(), t, n, X.stride(0), d_max, b, _prec(prec), _stream(stream),
                              ctypes.byref(out)))
-    return {"shape": out.shape, "target_items": out.target_items, "ms": out.ms}
+    return {"shape": out.shape, "target_items": out.target_items, "inner_b": out.inner_b, "ms": out.ms}
 
 
-def set_tuning(t: int, n: int, d_max: int, b: int, prec, shape=None, target_items=1024) -> None:
-    """Fix the launch configuration for a shape (shape=None forgets it)."""
+def get_tuning(t: int, n: int, d_max: int, b: int, prec) -> dict:
+    """The configuration cumulants() uses for this shape (tuned, else defaults)."""
+    out = Tuning()
+    _check(_lib.cum_get_tuning(t, n, d_max, b, _prec(prec), ctypes.byref(out)))
+    return {"shape": out.shape, "target_items": out.target_items, "inner_b": out.inner_b}
+
+
+def set_tuning(t: int, n: int, d_max: int, b: int, prec, shape=None, target_items=1024, inner_b=1) -> None:
+    """Fix the configuration for a shape (shape=None forgets it)."""
     if shape is None:
         _check(_lib.cum_set_tuning(t, n, d_max, b, _prec(prec), None))
         return
-    tune = Tuning(SHAPES[shape] if isinstance(shape, str) else int(shape), int(target_items), 0.0)
+    tune = Tuning(SHAPES[shape] if isinstance(shape, str) else int(shape), int(target_items), int(inner_b), 0.0)
     _check(_lib.cum_set_tuning(t, n, d_max, b, _prec(prec), ctypes.byref(tune)))
 
 
@@ -280,7 +289,7 @@ class Batch:
         xs = (_VP * len(X_list))(*[X.data_ptr() for X in X_list])
         out = Tuning()
         _check(_lib.cum_batch_autotune(self._h, xs, ctypes.byref(out)))
-        return {"shape": out.shape, "target_items": out.target_items, "ms": out.ms}
+        return {"shape": out.shape, "target_items": out.target_items, "inner_b": out.inner_b, "ms": out.ms}
 
     def timestamps(self):
         ns = len(self.t)

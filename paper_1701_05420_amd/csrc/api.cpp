@@ -186,13 +186,14 @@ struct OrderPlan {
     std::vector<int32_t> rb_vmin, cb_wmax;  // per 32-row / 32-column block
     std::vector<int32_t> rv16, cw16;        // per 16-row / 16-column block
     std::vector<int64_t> H;
+    std::vector<int64_t> prank;  // d x (nbar + 1): b^d * C(nbar - x + d - k - 1, d - k)
     std::vector<uint8_t> tuples;
     std::vector<uint16_t> parts;  // npart x MAXPARTS
     int npart = 0;
     std::vector<int32_t> loff;  // 2^d LDS offsets of staged sub-blocks (-1: not staged)
     int lds_elems = 0;          // 0: the recursion reads lower orders from memory
     bool uploaded = false;
-    DevBuf rows_d, cols_d, rbv_d, cbw_d, H_d, tuples_d, parts_d, loff_d;
+    DevBuf rows_d, cols_d, rbv_d, cbw_d, H_d, prank_d, tuples_d, parts_d, loff_d;
 };
 
 static cum_status build_order(int n, int b, int d, OrderPlan &o) {
@@ -294,6 +295,10 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
     o.H.assign((size_t)nbar * nbar, 0);
     for (int v = 0; v < nbar; ++v)
         for (int w = v; w < nbar; ++w) o.H[(size_t)v * nbar + w] = bd * rank_term(nbar, d, p, v, w);
+    // rank terms of a whole sorted tuple (rank = sum_k prank[k][j_(k-1)] - prank[k][j_k], j_(-1) = 0)
+    o.prank.assign((size_t)d * (nbar + 1), 0);
+    for (int k = 0; k < d; ++k)
+        for (int x = 0; x <= nbar; ++x) o.prank[(size_t)k * (nbar + 1) + x] = bd * binom(nbar - x + d - k - 1, d - k);
 
     // recursion tables
     auto T = sorted_tuples(nbar, d);
@@ -322,7 +327,8 @@ static cum_status upload_order(OrderPlan &o) {
     if (o.uploaded) return CUM_OK;
     cum_status st;
     if ((st = upload(o.rows_d, o.rows)) || (st = upload(o.cols_d, o.cols)) || (st = upload(o.rbv_d, o.rv16)) ||
-        (st = upload(o.cbw_d, o.cw16)) || (st = upload(o.H_d, o.H)) || (st = upload(o.tuples_d, o.tuples)) ||
+        (st = upload(o.cbw_d, o.cw16)) || (st = upload(o.H_d, o.H)) || (st = upload(o.prank_d, o.prank)) ||
+        (st = upload(o.tuples_d, o.tuples)) ||
         (st = upload(o.parts_d, o.parts)) || (st = upload(o.loff_d, o.loff)))
         return st;
     o.uploaded = true;
@@ -392,15 +398,62 @@ static void order_tiles(const OrderPlan &o, int wn, int ord_index, std::vector<H
 
 static int shape_wn(int shape) { return shape == TS_1x2 ? 2 : 1; }
 
+// Contraction record of an order (device pointers once uploaded).
+static OrderDev order_dev(const OrderPlan &o, int64_t off) {
+    OrderDev od;
+    od.rows = (const Feat *)o.rows_d.p;
+    od.cols = (const Feat *)o.cols_d.p;
+    od.rv16 = (const int32_t *)o.rbv_d.p;
+    od.cw16 = (const int32_t *)o.cbw_d.p;
+    od.H = (const int64_t *)o.H_d.p;
+    od.out_off = off;
+    od.elems = o.elems;
+    od.d = o.d;
+    od.p = o.p;
+    od.q = o.q;
+    od.nbar = o.nbar;
+    od.b = o.b;
+    od.nr = o.nr;
+    od.nc = o.nc;
+    od.pad = 0;
+    return od;
+}
+
+// Reduction record of an order: output layout o, partial sums in layout po
+// (the same plan, or the one of a smaller block size) at offset poff.
+static RedOrder red_order(const OrderPlan &o, const OrderPlan &po, int64_t poff) {
+    RedOrder ro;
+    memset(&ro, 0, sizeof ro);
+    ro.tuples = (const uint8_t *)o.tuples_d.p;
+    ro.parts = (const uint16_t *)o.parts_d.p;
+    ro.loff = o.lds_elems ? (const int32_t *)o.loff_d.p : nullptr;
+    ro.prank = (const int64_t *)po.prank_d.p;
+    ro.lds_elems = o.lds_elems;
+    ro.nblocks = o.nblocks;
+    ro.out_off = poff;
+    ro.d = o.d;
+    ro.npart = o.npart;
+    ro.nbar = o.nbar;
+    ro.b = o.b;
+    ro.pb = po.b;
+    ro.pnbar = po.nbar;
+    ro.n = o.n;
+    return ro;
+}
+
 // ---------------------------------------------------------------------------
 // call plan: all orders dlo..dhi of one (n, b), one precision and tile shape,
 // one sample count.
 // ---------------------------------------------------------------------------
 struct CallPlan {
-    int n = 0, b = 0, dlo = 0, dhi = 0, prec = 0, shape = 0;
-    int64_t t = 0, nstages = 0, chunk_stages = 0, nchunks = 0, stride = 0, nitems = 0;
-    std::vector<OrderPlan *> orders;  // index d - dlo
-    std::vector<int64_t> out_off;     // index d - dlo
+    int n = 0, b = 0, bi = 0, dlo = 0, dhi = 0, prec = 0, shape = 0;
+    int64_t t = 0, nstages = 0, chunk_stages = 0, nchunks = 0, nitems = 0;
+    int64_t stride = 0;               // partial sums of all orders, block size bi
+    int64_t kstride = 0;              // outputs of all orders, block size b
+    std::vector<OrderPlan *> orders;  // output layout (block size b), index d - dlo
+    std::vector<OrderPlan *> corders; // contraction layout (block size bi), index d - dlo
+    std::vector<int64_t> out_off;     // output offsets in a contiguous buffer, index d - dlo
+    std::vector<int64_t> pout_off;    // partial-sum offsets, index d - dlo
     std::vector<OrderDev> ods;
     std::vector<TileDev> tdev;
     std::vector<Item> items;
@@ -414,17 +467,12 @@ struct CallPlan {
 static cum_status upload_call(CallPlan &c) {
     if (c.uploaded) return CUM_OK;
     cum_status st;
+    c.ods.clear();
+    c.red.clear();
     for (size_t i = 0; i < c.orders.size(); ++i) {
-        OrderPlan *o = c.orders[i];
-        if ((st = upload_order(*o))) return st;
-        c.ods[i].rows = (const Feat *)o->rows_d.p;
-        c.ods[i].cols = (const Feat *)o->cols_d.p;
-        c.ods[i].rv16 = (const int32_t *)o->rbv_d.p;
-        c.ods[i].cw16 = (const int32_t *)o->cbw_d.p;
-        c.ods[i].H = (const int64_t *)o->H_d.p;
-        c.red[i].tuples = (const uint8_t *)o->tuples_d.p;
-        c.red[i].parts = (const uint16_t *)o->parts_d.p;
-        c.red[i].loff = o->lds_elems ? (const int32_t *)o->loff_d.p : nullptr;
+        if ((st = upload_order(*c.orders[i])) || (st = upload_order(*c.corders[i]))) return st;
+        c.ods.push_back(order_dev(*c.corders[i], c.pout_off[i]));
+        c.red.push_back(red_order(*c.orders[i], *c.corders[i], c.pout_off[i]));
     }
     if ((st = upload(c.ords_d, c.ods)) || (st = upload(c.tiles_d, c.tdev)) || (st = upload(c.items_d, c.items)) ||
         (st = upload(c.red_d, c.red)))
@@ -433,12 +481,13 @@ static cum_status upload_call(CallPlan &c) {
     return CUM_OK;
 }
 
-static std::map<std::tuple<int, int, int, int, int, int, int, int64_t>, std::unique_ptr<CallPlan>> g_calls;
+static std::map<std::tuple<int, int, int, int, int, int, int, int, int64_t>, std::unique_ptr<CallPlan>> g_calls;
 
-// Tuned choices: (n, b, dlo, dhi, prec, t) -> (shape, target items).
+// Tuned choices: (n, b, dlo, dhi, prec, t) -> (shape, target items, inner block size).
 struct Tuning {
     int shape;
     int target;
+    int bi;
 };
 static std::map<std::tuple<int, int, int, int, int, int64_t>, Tuning> g_tuned;
 static bool g_tune_loaded = false;
@@ -448,7 +497,8 @@ static const char *tune_file() {
     return (f && *f) ? f : nullptr;
 }
 
-// Cache file: one line per tuned shape, "n b dlo dhi prec t shape target".
+// Cache file: one line per tuned shape, "n b dlo dhi prec t shape target bi";
+// lines that do not parse, or name an invalid configuration, are skipped.
 static void load_tune_file() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
@@ -456,10 +506,15 @@ static void load_tune_file() {
     if (!f) return;
     FILE *fp = fopen(f, "r");
     if (!fp) return;
-    int n, b, dlo, dhi, prec, shape, target;
-    long long t;
-    while (fscanf(fp, "%d %d %d %d %d %lld %d %d", &n, &b, &dlo, &dhi, &prec, &t, &shape, &target) == 8)
-        g_tuned[std::make_tuple(n, b, dlo, dhi, prec, (int64_t)t)] = Tuning{shape, target};
+    char line[256];
+    while (fgets(line, sizeof line, fp)) {
+        int n, b, dlo, dhi, prec, shape, target, bi;
+        long long t;
+        if (sscanf(line, "%d %d %d %d %d %lld %d %d %d", &n, &b, &dlo, &dhi, &prec, &t, &shape, &target, &bi) != 9)
+            continue;
+        if ((shape != TS_1x1 && shape != TS_1x2) || target < 1 || bi < 1 || bi > b) continue;
+        g_tuned[std::make_tuple(n, b, dlo, dhi, prec, (int64_t)t)] = Tuning{shape, target, bi};
+    }
     fclose(fp);
 }
 
@@ -470,18 +525,21 @@ static void save_tune_file() {
     if (!fp) return;
     for (auto &kv : g_tuned) {
         auto &k = kv.first;
-        fprintf(fp, "%d %d %d %d %d %lld %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
-                std::get<4>(k), (long long)std::get<5>(k), kv.second.shape, kv.second.target);
+        fprintf(fp, "%d %d %d %d %d %lld %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                std::get<4>(k), (long long)std::get<5>(k), kv.second.shape, kv.second.target, kv.second.bi);
     }
     fclose(fp);
 }
 
 static int default_shape(int prec) { return prec == P_F32 ? TS_1x1 : TS_1x2; }
 constexpr int DEFAULT_TARGET = 1024;
+// The contraction computes each distinct sorted variable tuple once (inner
+// block size 1) unless tuning chose otherwise.
+static int default_inner(int) { return 1; }
 
-static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int shape, int target, int64_t t,
+static cum_status get_call_cfg(int n, int b, int bi, int dlo, int dhi, int prec, int shape, int target, int64_t t,
                                CallPlan **out) {
-    auto key = std::make_tuple(n, b, dlo, dhi, prec, shape, target, t);
+    auto key = std::make_tuple(n, b, bi, dlo, dhi, prec, shape, target, t);
     auto it = g_calls.find(key);
     if (it != g_calls.end()) {
         *out = it->second.get();
@@ -490,6 +548,7 @@ static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int sha
     std::unique_ptr<CallPlan> c(new CallPlan);
     c->n = n;
     c->b = b;
+    c->bi = bi;
     c->dlo = dlo;
     c->dhi = dhi;
     c->prec = prec;
@@ -498,47 +557,21 @@ static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int sha
     c->nstages = (t + stage_kt(prec) - 1) / stage_kt(prec);
     const int wn = shape_wn(shape);
     std::vector<HostTile> tiles;
-    int64_t off = 0;
+    int64_t off = 0, poff = 0;
     for (int d = dlo; d <= dhi; ++d) {
-        OrderPlan *o;
-        cum_status st = get_order(n, b, d, &o);
-        if (st) return st;
+        OrderPlan *o, *co;
+        cum_status st;
+        if ((st = get_order(n, b, d, &o)) || (st = get_order(n, bi, d, &co))) return st;
         c->orders.push_back(o);
+        c->corders.push_back(co);
         c->out_off.push_back(off);
-        OrderDev od;
-        od.rows = nullptr;
-        od.cols = nullptr;
-        od.rv16 = nullptr;
-        od.cw16 = nullptr;
-        od.H = nullptr;
-        od.out_off = off;
-        od.elems = o->elems;
-        od.d = d;
-        od.p = o->p;
-        od.q = o->q;
-        od.nbar = o->nbar;
-        od.b = b;
-        od.nr = o->nr;
-        od.nc = o->nc;
-        od.pad = 0;
-        c->ods.push_back(od);
-        order_tiles(*o, wn, d - dlo, tiles);
-        RedOrder ro;
-        memset(&ro, 0, sizeof ro);
-        ro.tuples = nullptr;
-        ro.parts = nullptr;
-        ro.loff = nullptr;
-        ro.lds_elems = o->lds_elems;
-        ro.nblocks = o->nblocks;
-        ro.out_off = off;
-        ro.d = d;
-        ro.npart = o->npart;
-        ro.nbar = o->nbar;
-        ro.b = b;
-        c->red.push_back(ro);
+        c->pout_off.push_back(poff);
+        order_tiles(*co, wn, d - dlo, tiles);
         off += o->elems;
+        poff += co->elems;
     }
-    c->stride = off;
+    c->kstride = off;
+    c->stride = poff;
     // expensive tiles first, so that the tail of each XCD's queue is short
     std::stable_sort(tiles.begin(), tiles.end(), [](const HostTile &x, const HostTile &y) { return x.cost > y.cost; });
     const int64_t ntiles = (int64_t)tiles.size();
@@ -584,8 +617,9 @@ static cum_status get_call_cfg(int n, int b, int dlo, int dhi, int prec, int sha
 static cum_status get_call(int n, int b, int dlo, int dhi, int prec, int64_t t, CallPlan **out) {
     load_tune_file();
     auto it = g_tuned.find(std::make_tuple(n, b, dlo, dhi, prec, t));
-    if (it != g_tuned.end()) return get_call_cfg(n, b, dlo, dhi, prec, it->second.shape, it->second.target, t, out);
-    return get_call_cfg(n, b, dlo, dhi, prec, default_shape(prec), DEFAULT_TARGET, t, out);
+    if (it != g_tuned.end())
+        return get_call_cfg(n, b, it->second.bi, dlo, dhi, prec, it->second.shape, it->second.target, t, out);
+    return get_call_cfg(n, b, default_inner(b), dlo, dhi, prec, default_shape(prec), DEFAULT_TARGET, t, out);
 }
 
 static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
@@ -795,7 +829,7 @@ cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, in
     hipStream_t s = (hipStream_t)stream;
     char *Xst = (char *)ws;
     HIP_TRY(timed(CUM_KIND_CENTER, s, [&] {
-        return launch_stage(Xc, t, n, n, nullptr, Xst, prec, false, prec == P_F64, s);
+        return launch_stage(Xc, t, n, n, nullptr, Xst, prec, false, prec == CUM_F64, s);
     }));
     double *outs[1] = {M};
     return run_orders(c, Xst, (double *)(Xst + xbytes), outs, false, s);
@@ -853,6 +887,16 @@ cum_status cum_plan_check(int n, int d, int b) {
     if ((st = build_order(n, b, d, o))) return st;  // host tables only, nothing uploaded
     const int64_t be = ipow64(b, d);
     auto T = sorted_tuples(o.nbar, d);
+    // the rank terms the reduction uses to find a tuple's partial sums
+    for (size_t i = 0; i < T.size(); ++i) {
+        int64_t r = 0;
+        int prev = 0;
+        for (int k = 0; k < d; ++k) {
+            r += o.prank[(size_t)k * (o.nbar + 1) + prev] - o.prank[(size_t)k * (o.nbar + 1) + T[i][k]];
+            prev = T[i][k];
+        }
+        if (r != (int64_t)i * be) return fail(CUM_EINVAL, "d=%d: rank table gives %lld for tuple %zu", d, (long long)r, i);
+    }
     for (int shape : {TS_1x1, TS_1x2}) {
         const int wn = shape_wn(shape);
         std::vector<HostTile> tiles;
@@ -915,13 +959,40 @@ cum_status cum_set_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, con
     if (tune->shape != TS_1x1 && tune->shape != TS_1x2)
         return fail(CUM_EINVAL, "unknown tile shape %d", tune->shape);
     if (tune->target_items < 1) return fail(CUM_EINVAL, "target_items must be >= 1");
-    g_tuned[key] = Tuning{tune->shape, tune->target_items};
+    if (tune->inner_b < 1 || tune->inner_b > b)
+        return fail(CUM_EINVAL, "inner_b must be in 1..b (got %d, b=%d)", tune->inner_b, b);
+    g_tuned[key] = Tuning{tune->shape, tune->target_items, tune->inner_b};
     return CUM_OK;
 }
 
-// Time every candidate (tile shape x work-item target) on the caller's data
-// and keep the fastest for this shape: the contraction plus the reduction and
-// recursion, best of three after one warm-up, HIP events on the stream.
+cum_status cum_get_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, cum_tuning *tune) {
+    cum_status st;
+    if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;
+    if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
+    if (!tune) return fail(CUM_EINVAL, "tune is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_tune_file();
+    auto it = g_tuned.find(std::make_tuple(n, b, 2, d_max, (int)prec, t));
+    const bool have = it != g_tuned.end();
+    tune->shape = have ? it->second.shape : default_shape(prec);
+    tune->target_items = have ? it->second.target : DEFAULT_TARGET;
+    tune->inner_b = have ? it->second.bi : default_inner(b);
+    tune->ms = 0.f;
+    return CUM_OK;
+}
+
+// Candidate inner block sizes: the caller's b, 2 and 1.
+static std::vector<int> inner_candidates(int b) {
+    std::vector<int> v{b};
+    if (b > 2) v.push_back(2);
+    if (b > 1) v.push_back(1);
+    return v;
+}
+
+// Time every candidate (inner block size x tile shape x work-item target) on
+// the caller's data and keep the fastest for this shape: the contraction plus
+// the reduction and recursion, best of three after one warm-up, HIP events on
+// the stream.
 cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec, void *stream,
                         cum_tuning *best) {
     cum_status st;
@@ -933,20 +1004,23 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     const int shapes[] = {TS_1x1, TS_1x2};
     const int targets[] = {512, 1024, 2048, 4096};
     std::vector<CallPlan *> cands;
+    std::vector<int> cand_target;
     size_t part_max = 0;
-    for (int sh : shapes)
-        for (int tg : targets) {
-            CallPlan *c;
-            if ((st = get_call_cfg(n, b, 2, d_max, prec, sh, tg, t, &c))) return st;
-            if ((st = upload_call(*c))) return st;
-            cands.push_back(c);
-            part_max = std::max(part_max, align_up((size_t)c->nchunks * c->stride * 8));
-        }
+    for (int bi : inner_candidates(b))
+        for (int sh : shapes)
+            for (int tg : targets) {
+                CallPlan *c;
+                if ((st = get_call_cfg(n, b, bi, 2, d_max, prec, sh, tg, t, &c))) return st;
+                if ((st = upload_call(*c))) return st;
+                cands.push_back(c);
+                cand_target.push_back(tg);
+                part_max = std::max(part_max, align_up((size_t)c->nchunks * c->stride * 8));
+            }
     int groups;
     int64_t rows_per;
     center_groups(t, groups, rows_per);
     const size_t xbytes = staged_bytes(t, n, prec), cbytes = align_up((size_t)groups * n * 2 * 8);
-    const size_t mbytes = align_up((size_t)n * 8), kbytes = align_up((size_t)cands[0]->stride * 8);
+    const size_t mbytes = align_up((size_t)n * 8), kbytes = align_up((size_t)cands[0]->kstride * 8);
     DevBuf ws;
     HIP_TRY(hipMalloc(&ws.p, xbytes + cbytes + mbytes + kbytes + part_max));
     char *w = (char *)ws.p;
@@ -988,12 +1062,13 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     HIP_TRY(hipStreamSynchronize(s));
     int best_target = 0;
     for (size_t i = 0; i < cands.size(); ++i)
-        if (cands[i] == best_c) best_target = targets[i % 4];
-    g_tuned[std::make_tuple(n, b, 2, d_max, (int)prec, t)] = Tuning{best_c->shape, best_target};
+        if (cands[i] == best_c) best_target = cand_target[i];
+    g_tuned[std::make_tuple(n, b, 2, d_max, (int)prec, t)] = Tuning{best_c->shape, best_target, best_c->bi};
     save_tune_file();
     if (best) {
         best->shape = best_c->shape;
         best->target_items = best_target;
+        best->inner_b = best_c->bi;
         best->ms = best_ms;
     }
     return CUM_OK;
@@ -1029,11 +1104,14 @@ cum_status cum_timing_read(double *ms, int64_t *launches) {
 // Batched cumulants.
 // ---------------------------------------------------------------------------
 struct cum_batch {
-    int nsets = 0, n = 0, d_max = 0, b = 0, prec = 0, shape = 0;
-    int64_t chunk_stages = 0, stride = 0, nitems = 0;
+    int nsets = 0, n = 0, d_max = 0, b = 0, bi = 0, prec = 0, shape = 0;
+    int64_t chunk_stages = 0, nitems = 0;
+    int64_t stride = 0;               // partial sums of all orders (block size bi)
+    int64_t kstride = 0;              // outputs of all orders (block size b)
     std::vector<int64_t> t;
-    std::vector<OrderPlan *> orders;  // d = 2..d_max
-    std::vector<int64_t> out_off;
+    std::vector<OrderPlan *> orders;  // output layout, d = 2..d_max
+    std::vector<OrderPlan *> corders; // contraction layout (block size bi)
+    std::vector<int64_t> out_off;     // output offsets in a contiguous buffer
     std::vector<OrderDev> ods;
     std::vector<RedOrder> red;
     std::vector<HostTile> tiles;
@@ -1102,13 +1180,29 @@ static std::vector<Item> batch_items(const cum_batch &p) {
     return items;
 }
 
-// (Re)build the tiles, chunking and items for a shape and target, and the
-// per-dataset records that depend on them.
-static cum_status batch_layout(cum_batch &p, int shape, int target) {
+// (Re)build the contraction tables, tiles, chunking and items for an inner
+// block size, shape and target, and the per-dataset records that depend on them.
+static cum_status batch_layout(cum_batch &p, int bi, int shape, int target) {
+    cum_status st;
     const int wn = shape_wn(shape);
     p.shape = shape;
+    p.bi = bi;
+    p.corders.clear();
+    p.ods.clear();
+    p.red.clear();
+    int64_t poff_o = 0;
+    for (size_t i = 0; i < p.orders.size(); ++i) {
+        OrderPlan *co;
+        if ((st = get_order(p.n, bi, p.orders[i]->d, &co)) || (st = upload_order(*co))) return st;
+        p.corders.push_back(co);
+        p.ods.push_back(order_dev(*co, poff_o));
+        p.red.push_back(red_order(*p.orders[i], *co, poff_o));
+        poff_o += co->elems;
+    }
+    p.stride = poff_o;
+    if ((st = upload(p.ords_d, p.ods)) || (st = upload(p.red_d, p.red))) return st;
     p.tiles.clear();
-    for (size_t i = 0; i < p.orders.size(); ++i) order_tiles(*p.orders[i], wn, (int)i, p.tiles);
+    for (size_t i = 0; i < p.corders.size(); ++i) order_tiles(*p.corders[i], wn, (int)i, p.tiles);
     std::stable_sort(p.tiles.begin(), p.tiles.end(), [](const HostTile &x, const HostTile &y) { return x.cost > y.cost; });
     const int KT = stage_kt(p.prec);
     int64_t total_st = 0, max_st = 1;
@@ -1133,7 +1227,6 @@ static cum_status batch_layout(cum_batch &p, int shape, int target) {
     }
     auto items = batch_items(p);
     p.nitems = (int64_t)items.size();
-    cum_status st;
     std::vector<TileDev> tdev;
     for (auto &h : p.tiles) tdev.push_back(h.t);
     if ((st = upload(p.tiles_d, tdev)) || (st = upload(p.items_d, items))) return st;
@@ -1146,6 +1239,7 @@ static cum_status batch_layout(cum_batch &p, int shape, int target) {
         p.sets[s].partial = (double *)p.partial_d.p + (int64_t)(intptr_t)p.sets[s].partial;
         p.setred[s].partial = p.sets[s].partial;
         p.setred[s].nchunks = p.sets[s].nchunks;
+        p.setred[s].stride = p.stride;
     }
     if ((st = upload(p.sets_d, p.sets))) return st;
     if (p.exec) {
@@ -1216,40 +1310,9 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
         if ((st = get_order(n, b, d, &o)) || (st = upload_order(*o))) return st;
         p->orders.push_back(o);
         p->out_off.push_back(off);
-        OrderDev od;
-        od.rows = (const Feat *)o->rows_d.p;
-        od.cols = (const Feat *)o->cols_d.p;
-        od.rv16 = (const int32_t *)o->rbv_d.p;
-        od.cw16 = (const int32_t *)o->cbw_d.p;
-        od.H = (const int64_t *)o->H_d.p;
-        od.out_off = off;
-        od.elems = o->elems;
-        od.d = d;
-        od.p = o->p;
-        od.q = o->q;
-        od.nbar = o->nbar;
-        od.b = b;
-        od.nr = o->nr;
-        od.nc = o->nc;
-        od.pad = 0;
-        p->ods.push_back(od);
-        RedOrder ro;
-        memset(&ro, 0, sizeof ro);
-        ro.tuples = (const uint8_t *)o->tuples_d.p;
-        ro.parts = (const uint16_t *)o->parts_d.p;
-        ro.loff = o->lds_elems ? (const int32_t *)o->loff_d.p : nullptr;
-        ro.lds_elems = o->lds_elems;
-        ro.nblocks = o->nblocks;
-        ro.out_off = off;
-        ro.d = d;
-        ro.npart = o->npart;
-        ro.nbar = o->nbar;
-        ro.b = b;
-        p->red.push_back(ro);
         off += o->elems;
     }
-    p->stride = off;
-    if ((st = upload(p->ords_d, p->ods)) || (st = upload(p->red_d, p->red))) return st;
+    p->kstride = off;
     // per-dataset storage: staged data, centring partial sums, means scratch
     const int KT = stage_kt(prec), KTP = stage_pitch(prec);
     int64_t staged = 0, parts = 0;
@@ -1284,7 +1347,6 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
         c.pad = 0;
         p->sets[s].X = c.Xc;
         SetRed &r = p->setred[s];
-        r.stride = off;
         r.t = p->t[s];
         for (int k = 0; k < MAXD - 1; ++k) r.kappa[k] = nullptr;
         r.stamp = (unsigned long long *)p->stamps_d.p + 1 + s;
@@ -1296,7 +1358,8 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
     auto tk = g_tuned.find(std::make_tuple(n, b, 2, d_max, (int)prec, -(int64_t)n_sets));
     const int shape = tk != g_tuned.end() ? tk->second.shape : default_shape(prec);
     const int target = tk != g_tuned.end() ? tk->second.target : 16384;
-    if ((st = batch_layout(*p, shape, target))) return st;
+    const int bi = tk != g_tuned.end() ? tk->second.bi : default_inner(b);
+    if ((st = batch_layout(*p, bi, shape, target))) return st;
     HIP_TRY(hipMalloc(&p->cset_d.p, sizeof(CenterSet) * n_sets));
     HIP_TRY(hipMalloc(&p->setred_d.p, sizeof(SetRed) * n_sets));
     HIP_TRY(hipHostMalloc((void **)&p->h_cset, sizeof(CenterSet) * n_sets, hipHostMallocDefault));
@@ -1369,61 +1432,70 @@ cum_status cum_batch_timestamps(cum_batch *p, uint64_t *start, uint64_t *ticks, 
     return CUM_OK;
 }
 
-// Time the moment launch of every candidate (tile shape x work-item target)
-// on the batch's data and keep the fastest; the graph is captured again on
-// the next run.
+// Time the whole graph of every candidate (inner block size x tile shape x
+// work-item target) on the batch's data and keep the fastest; the graph is
+// captured again on the next run.
 cum_status cum_batch_autotune(cum_batch *p, const double *const *X_i, cum_tuning *best) {
     if (!p || !X_i) return fail(CUM_EINVAL, "NULL argument");
     std::vector<double *> kap((size_t)p->nsets * (p->d_max - 1));
     // outputs of the trial runs go to a scratch buffer shared by all datasets
     DevBuf scratch;
-    HIP_TRY(hipMalloc(&scratch.p, (size_t)p->stride * sizeof(double)));
+    HIP_TRY(hipMalloc(&scratch.p, (size_t)p->kstride * sizeof(double)));
     for (int s = 0; s < p->nsets; ++s)
         for (int d = 2; d <= p->d_max; ++d) kap[(size_t)s * (p->d_max - 1) + d - 2] = (double *)scratch.p + p->out_off[d - 2];
     const int shapes[] = {TS_1x1, TS_1x2};
     const int targets[] = {4096, 16384, 65536};
     float best_ms = 1e30f;
-    int best_shape = p->shape, best_target = 16384;
+    int best_shape = p->shape, best_target = 16384, best_bi = p->bi;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    struct Cand {
+        int bi, sh, tg;
+    };
+    std::vector<Cand> cands;
+    for (int bi : inner_candidates(p->b))
+        for (int sh : shapes)
+            for (int tg : targets) cands.push_back({bi, sh, tg});
     cum_status st = CUM_OK;
-    for (int sh : shapes)
-        for (int tg : targets) {
-            {
-                std::lock_guard<std::mutex> lk(g_mu);
-                if ((st = batch_layout(*p, sh, tg))) break;
-            }
-            float ms_best = 1e30f;
-            for (int rep = 0; rep < 3 && !st; ++rep) {
-                if ((st = cum_batch_run(p, X_i, kap.data(), nullptr, nullptr))) break;
-                HIP_TRY(hipStreamSynchronize(p->stream));
-                HIP_TRY(hipEventRecord(e0, p->stream));
-                HIP_TRY(hipGraphLaunch(p->exec, p->stream));
-                HIP_TRY(hipEventRecord(e1, p->stream));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                ms_best = std::min(ms_best, ms);
-            }
-            if (st) break;
-            if (ms_best < best_ms) {
-                best_ms = ms_best;
-                best_shape = sh;
-                best_target = tg;
-            }
+    for (const Cand &cd : cands) {
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            if ((st = batch_layout(*p, cd.bi, cd.sh, cd.tg))) break;
         }
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 3 && !st; ++rep) {
+            if ((st = cum_batch_run(p, X_i, kap.data(), nullptr, nullptr))) break;
+            HIP_TRY(hipStreamSynchronize(p->stream));
+            HIP_TRY(hipEventRecord(e0, p->stream));
+            HIP_TRY(hipGraphLaunch(p->exec, p->stream));
+            HIP_TRY(hipEventRecord(e1, p->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            ms_best = std::min(ms_best, ms);
+        }
+        if (st) break;
+        if (ms_best < best_ms) {
+            best_ms = ms_best;
+            best_shape = cd.sh;
+            best_target = cd.tg;
+            best_bi = cd.bi;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_TRY(hipDeviceSynchronize());
     if (st) return st;
     std::lock_guard<std::mutex> lk(g_mu);
-    if ((st = batch_layout(*p, best_shape, best_target))) return st;
-    g_tuned[std::make_tuple(p->n, p->b, 2, p->d_max, p->prec, -(int64_t)p->nsets)] = Tuning{best_shape, best_target};
+    if ((st = batch_layout(*p, best_bi, best_shape, best_target))) return st;
+    g_tuned[std::make_tuple(p->n, p->b, 2, p->d_max, p->prec, -(int64_t)p->nsets)] =
+        Tuning{best_shape, best_target, best_bi};
     save_tune_file();
     if (best) {
         best->shape = best_shape;
         best->target_items = best_target;
+        best->inner_b = best_bi;
         best->ms = best_ms;
     }
     return CUM_OK;

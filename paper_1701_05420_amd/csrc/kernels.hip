@@ -728,24 +728,16 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
             __syncthreads();
         }
         double *out = kap[d - 2];
+        // The partial sums are either in this layout (one per stored copy) or
+        // in the layout of block size pb, which holds each sorted variable
+        // tuple once; then every stored copy reads that tuple's sums.
+        const bool canon = ro.pb != b;
+        bool need_sort = false;  // equal adjacent blocks: the variables need sorting
+        for (int k = 0; k + 1 < d; ++k) need_sort |= tup[k] == tup[k + 1];
         for (int64_t o = tid; o < be; o += 256) {
             const int64_t e = B * be + o;
-            const double *pp = partial + ro.out_off + e;
-            double S = 0.0;
-            int64_t c = 0;
-            // eight independent loads in flight, summed in chunk order
-            for (; c + 8 <= nchunks; c += 8) {
-                double v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = pp[(c + u) * stride];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) S += v[u];
-            }
-            for (; c < nchunks; ++c) S += pp[c * stride];
-            const double M = S / tt;
-            double res = M;
-            if (rec) {
-                int r[MAXD];  // in-block digits, first position most significant
+            int r[MAXD];  // in-block digits, first position most significant
+            if (rec || canon) {
                 int64_t oo = o;
 #pragma unroll
                 for (int k = MAXD - 1; k >= 0; --k)
@@ -753,6 +745,61 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
                         r[k] = (int)(oo % b);
                         oo /= b;
                     }
+            }
+            int64_t poff = e;
+            bool pad = false;
+            if (canon) {
+                int u[MAXD];
+#pragma unroll
+                for (int k = 0; k < MAXD; ++k) u[k] = k < d ? tup[k] * b + r[k] : INT_MAX;
+                if (need_sort) {
+                    // odd-even transposition network: MAXD rounds sort MAXD keys
+#pragma unroll
+                    for (int rd = 0; rd < MAXD; ++rd)
+#pragma unroll
+                        for (int k = rd & 1; k + 1 < MAXD; k += 2) {
+                            const int lo = min(u[k], u[k + 1]), hi = max(u[k], u[k + 1]);
+                            u[k] = lo;
+                            u[k + 1] = hi;
+                        }
+                }
+                int umax = 0;
+#pragma unroll
+                for (int k = 0; k < MAXD; ++k)
+                    if (k < d) umax = max(umax, u[k]);
+                pad = umax >= ro.n;  // a padded position of a ragged block: M = 0
+                if (!pad) {
+                    const int pb = ro.pb, w = ro.pnbar + 1;
+                    int64_t rank = 0, in = 0;
+                    int prev = 0;
+#pragma unroll
+                    for (int k = 0; k < MAXD; ++k)
+                        if (k < d) {
+                            const int jb = pb == 1 ? u[k] : u[k] / pb;
+                            rank += ro.prank[k * w + prev] - ro.prank[k * w + jb];
+                            in = in * pb + (u[k] - jb * pb);
+                            prev = jb;
+                        }
+                    poff = rank + in;
+                }
+            }
+            double S = 0.0;
+            if (!pad) {
+                const double *pp = partial + ro.out_off + poff;
+                int64_t c = 0;
+                // eight independent loads in flight, summed in chunk order
+                for (; c + 8 <= nchunks; c += 8) {
+                    double v[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) v[q] = pp[(c + q) * stride];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) S += v[q];
+                }
+                for (; c < nchunks; ++c) S += pp[c * stride];
+            }
+            const double M = S / tt;
+            double res = M;
+            if (rec) {
                 double sum = 0.0;
                 for (int z = 0; z < ro.npart; ++z) {
                     double prod = 1.0;

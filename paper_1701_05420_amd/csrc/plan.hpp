@@ -112,11 +112,14 @@ struct RedOrder {
     const uint16_t *parts;  // npart x MAXPARTS position masks (0 = unused)
     const int32_t *loff;    // 2^d: LDS offset of the staged sub-block of each position
                             // mask of 2..d-2 positions (null: read them from memory)
+    const int64_t *prank;   // d x (pnbar + 1) rank terms of the partial-sum layout:
+                            // prank[k][x] = pb^d * C(pnbar - x + d - k - 1, d - k)
     int64_t nblocks;
     int64_t out_off;        // offset of this order in the per-chunk partial vector
     int32_t d, npart, nbar, b;
     int32_t lds_elems;      // doubles staged per block (0 without staging)
-    int32_t pad;
+    int32_t pb, pnbar;      // block size and blocks per mode of the partial-sum layout
+    int32_t n;              // variables
 };
 constexpr int RED_LDS_MAX = 6144;  // doubles of lower-order sub-blocks staged per block (48 KiB)
 

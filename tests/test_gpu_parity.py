@@ -80,6 +80,28 @@ def test_integer_data_bit_exact(dev, orc, prec, n, b, shift):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,b,dmax", [(9, 4, 5), (7, 3, 6), (10, 5, 4)])
+def test_inner_block_sizes_integer_exact(dev, orc, prec, n, b, dmax):
+    """Every inner block size of the contraction gives the exact cumulants."""
+    torch, pc = dev
+    t = 256
+    X = workloads.dyadic_integers(t=t, n=n, seed=n * b, lo=-2, hi=2) + 1.0
+    _, OK = orc.cumulants_dense(X, dmax)
+    Xd = torch.from_numpy(X).cuda()
+    for bi in range(1, b + 1):
+        say(f"inner block size prec={prec} n={n} b={b} dmax={dmax} inner_b={bi}")
+        pc.set_tuning(t, n, dmax, b, prec, "32x64", 1024, inner_b=bi)
+        _, K = pc.cumulants(Xd, dmax, b, prec)
+        for d in range(2, dmax + 1):
+            want = orc.fold(OK[d], b)
+            got = K[d].cpu().numpy()
+            assert np.array_equal(got, want), (bi, d, np.abs(got - want).max())
+    pc.set_tuning(t, n, dmax, b, prec, None)
+    with pytest.raises(pc.CumulantError):
+        pc.set_tuning(t, n, dmax, b, prec, "32x64", 1024, inner_b=b + 1)
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_unfold_integer_exact(dev, orc, prec):
     torch, pc = dev
     say(f"unfold prec={prec}")
@@ -137,6 +159,15 @@ def test_moment_blocks_multi_tile_sampled(dev, orc, prec):
         e = rel(M[offs], want)
         say(f"  moment e_{d} = {e:.3e}")
         assert e <= TOL[prec], (d, e)
+        if d == 3:
+            # each distinct variable tuple is summed once: every stored copy
+            # holds exactly the value of the canonical (sorted) copy
+            all_offs = np.arange(M.size)
+            idx = orc.block_indices(n, d, b, all_offs)
+            real = idx[:, 0] >= 0
+            canon = np.array([pc.stored_offset(n, d, b, list(ix)) for ix in idx[real]])
+            assert np.array_equal(M[all_offs[real]], M[canon])
+            assert not np.any(M[all_offs[~real]])
 
 
 # ---------------------------------------------------------------- properties
@@ -203,19 +234,20 @@ def test_autotune_and_tuned_configs(dev, orc):
     offs_idx = {d: stored_sample(orc, 24, d, 4, 200, seed=d) for d in range(2, 6)}
     want = {d: orc.cumulant_at(Xc, offs_idx[d][1]) for d in offs_idx}
     for prec in PRECS:
-        for shape in ["32x32", "32x64"]:
-            for target in [256, 1024, 4096]:
-                say(f"tuned prec={prec} shape={shape} target={target}")
-                pc.set_tuning(30_000, 24, 5, 4, prec, shape, target)
-                _, K1 = pc.cumulants(Xd, 5, 4, prec)
-                _, K2 = pc.cumulants(Xd, 5, 4, prec)
-                for d in range(2, 6):
-                    g = K1[d].cpu().numpy()
-                    assert np.array_equal(g, K2[d].cpu().numpy())
-                    e = rel(g[offs_idx[d][0]], want[d])
-                    assert e <= TOL[prec], (prec, shape, target, d, e)
+        for bi in [4, 2, 1]:
+            for shape in ["32x32", "32x64"]:
+                for target in [256, 1024, 4096]:
+                    say(f"tuned prec={prec} inner_b={bi} shape={shape} target={target}")
+                    pc.set_tuning(30_000, 24, 5, 4, prec, shape, target, inner_b=bi)
+                    _, K1 = pc.cumulants(Xd, 5, 4, prec)
+                    _, K2 = pc.cumulants(Xd, 5, 4, prec)
+                    for d in range(2, 6):
+                        g = K1[d].cpu().numpy()
+                        assert np.array_equal(g, K2[d].cpu().numpy())
+                        e = rel(g[offs_idx[d][0]], want[d])
+                        assert e <= TOL[prec], (prec, bi, shape, target, d, e)
         pc.set_tuning(30_000, 24, 5, 4, prec, None)
         best = pc.autotune(Xd, 5, 4, prec)
         say(f"autotune {prec}: {best}")
-        assert best["shape"] in (0, 2) and best["ms"] > 0
+        assert best["shape"] in (0, 2) and best["ms"] > 0 and 1 <= best["inner_b"] <= 4
         pc.set_tuning(30_000, 24, 5, 4, prec, None)

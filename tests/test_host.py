@@ -6,6 +6,7 @@ import math
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -117,8 +118,52 @@ def test_entry_points_validate_before_touching_the_device(pc):
     assert _raw(pc, "cum_cumulants", P, 10, 4, 4, 4, 2, 0, N, kap_null, P, 1 << 30, N) == -1
     assert _raw(pc, "cum_cumulants", N, 10, 4, 4, 4, 2, 0, N, kap, P, 1 << 30, N) == -1
     assert _raw(pc, "cum_cumulants", P, 10, 4, 4, 4, 2, 0, N, kap, P, 16, N) == -2          # workspace
+    assert b"workspace" in pc._lib.cum_last_error()
     assert _raw(pc, "cum_moment_blocks", P, 0, 10, 4, 1, 2, P, P, 1 << 30, N) == -1         # d = 1
     assert _raw(pc, "cum_moment_blocks", P, 0, 10, 4, 4, 2, P, P, 8, N) == -2
     assert _raw(pc, "cum_center", P, 10, 4, 2, 0, P, P, P, 1 << 20, N) == -1                # ldx < n
     assert _raw(pc, "cum_unfold", P, 4, 11, 2, P, N) == -1
-    assert b"workspace" in pc._lib.cum_last_error() or True
+
+
+def test_tuning_round_trip_and_validation(pc):
+    shape = (1000, 12, 4, 3, "f32")
+    pc.set_tuning(*shape, None)
+    assert pc.get_tuning(*shape) == {"shape": 0, "target_items": 1024, "inner_b": 1}
+    pc.set_tuning(*shape, "32x64", 2048, inner_b=3)
+    assert pc.get_tuning(*shape) == {"shape": 2, "target_items": 2048, "inner_b": 3}
+    for bad in [dict(inner_b=0), dict(inner_b=4), dict(target_items=0)]:
+        with pytest.raises(pc.CumulantError):
+            pc.set_tuning(*shape, "32x32", **{"target_items": 512, **bad})
+    with pytest.raises(pc.CumulantError):
+        pc.set_tuning(*shape, 1, 512)  # no such tile shape
+    assert pc.get_tuning(*shape)["target_items"] == 2048  # refused settings change nothing
+    pc.set_tuning(*shape, None)
+    # the workspace follows the chosen partial-sum layout
+    pc.set_tuning(100_000, 48, 4, 4, "f32", "32x32", 1024, inner_b=4)
+    big = pc.workspace_size(100_000, 48, 4, 4, "f32")
+    pc.set_tuning(100_000, 48, 4, 4, "f32", "32x32", 1024, inner_b=1)
+    small = pc.workspace_size(100_000, 48, 4, 4, "f32")
+    pc.set_tuning(100_000, 48, 4, 4, "f32", None)
+    assert small < big
+
+
+def test_tune_file_is_read_and_bad_lines_skipped(tmp_path):
+    """The cache file: one "n b dlo dhi prec t shape target inner_b" line per
+    shape; lines that do not parse or name an invalid choice are skipped."""
+    f = tmp_path / "tune.txt"
+    f.write_text("12 3 2 4 1 1000 2 4096 2\n"     # valid
+                 "12 3 2 5 1 1000 2 4096\n"       # too few fields
+                 "12 3 2 6 1 1000 2 4096 7\n"     # inner_b > b
+                 "12 3 2 7 1 1000 5 4096 1\n")    # unknown shape
+    code = ("import paper_1701_05420_amd as pc\n"
+            "print(pc.get_tuning(1000, 12, 4, 3, 'f32'))\n"
+            "print(pc.get_tuning(1000, 12, 5, 3, 'f32'))\n"
+            "print(pc.get_tuning(1000, 12, 6, 3, 'f32'))\n"
+            "print(pc.get_tuning(1000, 12, 7, 3, 'f32'))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, CUM_TUNE_FILE=str(f), PYTHONPATH=root)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True,
+                         timeout=120).stdout.splitlines()
+    assert out[0] == "{'shape': 2, 'target_items': 4096, 'inner_b': 2}"
+    for line in out[1:]:
+        assert line == "{'shape': 0, 'target_items': 1024, 'inner_b': 1}"
