@@ -670,7 +670,16 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
     ma.pad = 0;
     if (c->nitems > 0)
         HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, c->dhi, ma, (int)c->nitems, s); }));
-    // reduction (+ recursion) in pairs of orders {d, d+1}: order d needs
+    // the sum over sample chunks, once for all orders
+    SetRed sr0;
+    memset(&sr0, 0, sizeof sr0);
+    sr0.partial = partial;
+    sr0.stride = c->stride;
+    sr0.nchunks = c->nchunks;
+    sr0.t = c->t;
+    if (c->nchunks > 1)
+        HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_chunksum(nullptr, sr0, 1, c->stride, s); }));
+    // finalisation (+ recursion) in pairs of orders {d, d+1}: order d needs
     // cumulants up to d-2 only, so a pair depends only on earlier pairs
     const RedOrder *red_d = (const RedOrder *)c->red_d.p;
     for (int d = c->dlo; d <= c->dhi; d += 2) {
@@ -679,6 +688,7 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
         ra.ords = red_d + i0;
         ra.nords = (d + 1 <= c->dhi) ? 2 : 1;
         ra.recursion = recursion ? 1 : 0;
+        ra.presummed = 1;
         ra.nb0 = c->red[i0].nblocks;
         ra.nbtot = ra.nb0 + (ra.nords == 2 ? c->red[i0 + 1].nblocks : 0);
         ra.sets = nullptr;
@@ -1268,6 +1278,9 @@ static cum_status batch_enqueue(cum_batch &p, hipStream_t s) {
     ma.sets = (const SetDev *)p.sets_d.p;
     ma.n = p.n;
     if (p.nitems > 0) HIP_TRY(launch_moment(p.prec, p.shape, p.d_max, ma, (int)p.nitems, s));
+    SetRed none;
+    memset(&none, 0, sizeof none);
+    HIP_TRY(launch_chunksum((const SetRed *)p.setred_d.p, none, p.nsets, p.stride, s));
     const RedOrder *red_d = (const RedOrder *)p.red_d.p;
     for (int d = 2; d <= p.d_max; d += 2) {
         RedArgs ra;
@@ -1276,6 +1289,7 @@ static cum_status batch_enqueue(cum_batch &p, hipStream_t s) {
         ra.ords = red_d + i0;
         ra.nords = (d + 1 <= p.d_max) ? 2 : 1;
         ra.recursion = 1;
+        ra.presummed = 1;
         ra.nb0 = p.red[i0].nblocks;
         ra.nbtot = ra.nb0 + (ra.nords == 2 ? p.red[i0 + 1].nblocks : 0);
         ra.sets = (const SetRed *)p.setred_d.p;

@@ -690,7 +690,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
     for (int k = 0; k < MAXD - 1; ++k)
         if (tid == k) kap[k] = sr.kappa[k];
     const double *partial = sr.partial;
-    const int64_t stride = sr.stride, nchunks = sr.nchunks;
+    const int64_t stride = sr.stride, nchunks = a.presummed ? 1 : sr.nchunks;
     const double tt = (double)sr.t;
     for (int64_t gb = blockIdx.x; gb < a.nbtot; gb += gridDim.x) {
         const int oi = gb < a.nb0 ? 0 : 1;
@@ -821,6 +821,38 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
         }
         if (sr.stamp && tid == 0) atomicMax(sr.stamp, (unsigned long long)wall_clock64());
     }
+}
+
+// Sum of the per-chunk partial sums of every entry, in chunk order (Alg. 3's
+// reduction), into the entry's chunk-0 slot: one coalesced pass, so that the
+// finalisation reads one value per entry.
+__global__ __launch_bounds__(256) void chunksum_kernel(const SetRed *sets, SetRed set0, int64_t entries) {
+    const SetRed sr = sets ? sets[blockIdx.y] : set0;
+    const int64_t stride = sr.stride, nchunks = sr.nchunks;
+    if (nchunks <= 1) return;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < entries; e += (int64_t)gridDim.x * 256) {
+        const double *pp = sr.partial + e;
+        double S = 0.0;
+        int64_t c = 0;
+        // eight independent loads in flight, summed in chunk order
+        for (; c + 8 <= nchunks; c += 8) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = pp[(c + q) * stride];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) S += v[q];
+        }
+        for (; c < nchunks; ++c) S += pp[c * stride];
+        sr.partial[e] = S;
+    }
+}
+
+hipError_t launch_chunksum(const SetRed *sets, const SetRed &set0, int nsets, int64_t entries, hipStream_t s) {
+    int64_t gx = (entries + 255) / 256;
+    if (gx > 16384) gx = 16384;
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(chunksum_kernel, dim3((unsigned)gx, (unsigned)nsets), dim3(256), 0, s, sets, set0, entries);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_doubles, hipStream_t s) {

@@ -24,6 +24,7 @@ struct RedArgs {
     const RedOrder *ords;  // the orders finalised by this launch (1 or 2)
     int32_t nords;
     int32_t recursion;  // 0: plain moments (no cumulant recursion)
+    int32_t presummed;  // 1: chunk 0 of the partial sums already holds their sum
     int64_t nb0;   // blocks of the first order
     int64_t nbtot; // blocks of all orders of the launch
     const SetRed *sets;  // per-dataset records (grid.y), or null: set0
@@ -39,6 +40,7 @@ hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const doub
                         bool center, bool in_f64, hipStream_t s);
 hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s);
 hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_doubles, hipStream_t s);
+hipError_t launch_chunksum(const SetRed *sets, const SetRed &set0, int nsets, int64_t entries, hipStream_t s);
 hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,
                          hipStream_t s);
 hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s);

@@ -124,7 +124,7 @@ struct RedOrder {
 constexpr int RED_LDS_MAX = 6144;  // doubles of lower-order sub-blocks staged per block (48 KiB)
 
 struct SetRed {
-    const double *partial;
+    double *partial;               // nchunks x stride; chunk 0 receives the sums
     int64_t stride;
     int64_t nchunks;
     int64_t t;
