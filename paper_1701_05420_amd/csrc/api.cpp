@@ -16,6 +16,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -188,12 +189,14 @@ struct OrderPlan {
     std::vector<int64_t> H;
     std::vector<int64_t> prank;  // d x (nbar + 1): b^d * C(nbar - x + d - k - 1, d - k)
     std::vector<uint8_t> tuples;
-    std::vector<uint16_t> parts;  // npart x MAXPARTS
+    std::vector<int32_t> parts;   // npart x (d/2), packed mask | where << 10
     int npart = 0;
-    std::vector<int32_t> loff;  // 2^d LDS offsets of staged sub-blocks (-1: not staged)
-    int lds_elems = 0;          // 0: the recursion reads lower orders from memory
+    std::vector<uint16_t> smask;  // position sets of 2..d-2 positions, by size then value
+    std::vector<int32_t> gmap;    // staged slot -> s | flat << 10
+    int32_t mstart[MAXD] = {0};   // first staged slot of each set size m (index m - 2)
+    int lds_elems = 0;            // 0: the recursion reads lower orders from memory
     bool uploaded = false;
-    DevBuf rows_d, cols_d, rbv_d, cbw_d, H_d, prank_d, tuples_d, parts_d, loff_d;
+    DevBuf rows_d, cols_d, rbv_d, cbw_d, H_d, prank_d, tuples_d, parts_d, smask_d, gmap_d;
 };
 
 static cum_status build_order(int n, int b, int d, OrderPlan &o) {
@@ -304,21 +307,41 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
     auto T = sorted_tuples(nbar, d);
     for (const auto &u : T)
         for (int k = 0; k < d; ++k) o.tuples.push_back((uint8_t)u[k]);
+    // the recursion of a block reads, for every set S of 2..d-2 positions,
+    // the lower-order block j_S: the sets by size, and their sub-blocks'
+    // slots in LDS when they all fit
+    std::vector<int> sidx((size_t)1 << d, -1);
+    std::vector<int64_t> soff;
+    int64_t lds = 0;
+    for (int m = 2; m <= d - 2; ++m) {
+        o.mstart[m - 2] = (int32_t)std::min<int64_t>(lds, INT32_MAX);
+        for (int mask = 0; mask < (1 << d); ++mask) {
+            if (__builtin_popcount(mask) != m) continue;
+            sidx[(size_t)mask] = (int)o.smask.size();
+            o.smask.push_back((uint16_t)mask);
+            soff.push_back(lds);
+            lds += ipow64(b, m);
+        }
+    }
+    if (d >= 4) o.mstart[d - 3] = (int32_t)std::min<int64_t>(lds, INT32_MAX);
+    o.lds_elems = (d >= 4 && lds <= RED_LDS_MAX) ? (int)lds : 0;
+    if (o.lds_elems)
+        for (size_t si = 0; si < o.smask.size(); ++si) {
+            const int64_t sz = ipow64(b, __builtin_popcount(o.smask[si]));
+            for (int64_t f = 0; f < sz; ++f) o.gmap.push_back((int32_t)(si | (f << 10)));
+        }
     auto parts = recursion_partitions(d);
     o.npart = (int)parts.size();
+    const int per = d / 2;
     for (const auto &pm : parts)
-        for (int k = 0; k < MAXPARTS; ++k) o.parts.push_back(k < (int)pm.size() ? pm[k] : 0);
-    // the recursion of a block reads, for every set S of 2..d-2 positions,
-    // the lower-order block j_S: stage them all in LDS when they fit
-    o.loff.assign((size_t)1 << d, -1);
-    int64_t lds = 0;
-    for (int mask = 0; mask < (1 << d); ++mask) {
-        const int m = __builtin_popcount(mask);
-        if (d < 4 || m < 2 || m > d - 2) continue;
-        o.loff[mask] = (int32_t)lds;
-        lds += ipow64(b, m);
-    }
-    o.lds_elems = (d >= 4 && lds <= RED_LDS_MAX) ? (int)lds : 0;
+        for (int k = 0; k < per; ++k) {
+            int32_t v = 0;
+            if (k < (int)pm.size()) {
+                const int where = o.lds_elems ? (int)soff[(size_t)sidx[pm[k]]] : sidx[pm[k]];
+                v = (int32_t)pm[k] | (int32_t)(where << 10);
+            }
+            o.parts.push_back(v);
+        }
 
     return CUM_OK;
 }
@@ -329,7 +352,8 @@ static cum_status upload_order(OrderPlan &o) {
     if ((st = upload(o.rows_d, o.rows)) || (st = upload(o.cols_d, o.cols)) || (st = upload(o.rbv_d, o.rv16)) ||
         (st = upload(o.cbw_d, o.cw16)) || (st = upload(o.H_d, o.H)) || (st = upload(o.prank_d, o.prank)) ||
         (st = upload(o.tuples_d, o.tuples)) ||
-        (st = upload(o.parts_d, o.parts)) || (st = upload(o.loff_d, o.loff)))
+        (st = upload(o.parts_d, o.parts)) || (st = upload(o.smask_d, o.smask)) ||
+        (st = upload(o.gmap_d, o.gmap)))
         return st;
     o.uploaded = true;
     return CUM_OK;
@@ -425,10 +449,13 @@ static RedOrder red_order(const OrderPlan &o, const OrderPlan &po, int64_t poff)
     RedOrder ro;
     memset(&ro, 0, sizeof ro);
     ro.tuples = (const uint8_t *)o.tuples_d.p;
-    ro.parts = (const uint16_t *)o.parts_d.p;
-    ro.loff = o.lds_elems ? (const int32_t *)o.loff_d.p : nullptr;
+    ro.parts = (const int32_t *)o.parts_d.p;
+    ro.smask = (const uint16_t *)o.smask_d.p;
+    ro.gmap = (const int32_t *)o.gmap_d.p;
     ro.prank = (const int64_t *)po.prank_d.p;
+    ro.ns = (int32_t)o.smask.size();
     ro.lds_elems = o.lds_elems;
+    for (int k = 0; k < MAXD; ++k) ro.mstart[k] = o.mstart[k];
     ro.nblocks = o.nblocks;
     ro.out_off = poff;
     ro.d = o.d;
@@ -561,6 +588,8 @@ static cum_status get_call_cfg(int n, int b, int bi, int dlo, int dhi, int prec,
     for (int d = dlo; d <= dhi; ++d) {
         OrderPlan *o, *co;
         cum_status st;
+        if (ipow64(b, d) > INT32_MAX)
+            return fail(CUM_EUNSUPPORTED, "blocks of b^d = %d^%d entries (2^31 or more) are not supported", b, d);
         if ((st = get_order(n, b, d, &o)) || (st = get_order(n, bi, d, &co))) return st;
         c->orders.push_back(o);
         c->corders.push_back(co);
@@ -648,6 +677,25 @@ static cum_status check_prec(int prec) {
     return CUM_OK;
 }
 
+// Dynamic LDS of a finalisation launch over orders ro[0..nords-1]: the
+// staged sub-blocks, the block's lower-order offsets and, when everything
+// fits in 64 KiB, the partition table.  Fills the layout fields of ra and
+// returns the bytes to allocate.
+static int red_lds_layout(const RedOrder *ro, int nords, bool recursion, RedArgs &ra) {
+    int64_t sub = 0, ns = 0, parts = 0;
+    if (recursion)
+        for (int i = 0; i < nords; ++i) {
+            sub = std::max<int64_t>(sub, ro[i].lds_elems);
+            ns = std::max<int64_t>(ns, ro[i].ns);
+            parts = std::max<int64_t>(parts, (int64_t)ro[i].npart * (ro[i].d / 2));
+        }
+    ra.base_off = (int32_t)((sub * 8 + 15) / 16 * 16);
+    ra.parts_off = ra.base_off + (int32_t)((ns * 8 + 15) / 16 * 16);
+    ra.parts_lds = (parts > 0 && ra.parts_off + parts * 4 <= 65536) ? 1 : 0;
+    ra.pad = 0;
+    return ra.parts_off + (ra.parts_lds ? (int)(parts * 4) : 0);
+}
+
 // moment contraction + reduction for orders dlo..dhi into kappa (and the
 // recursion for d >= 4 when recursion is set)
 static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, double *const *outs, bool recursion,
@@ -684,9 +732,11 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
     const RedOrder *red_d = (const RedOrder *)c->red_d.p;
     for (int d = c->dlo; d <= c->dhi; d += 2) {
         RedArgs ra;
+        memset(&ra, 0, sizeof ra);
         const int i0 = d - c->dlo;
         ra.ords = red_d + i0;
         ra.nords = (d + 1 <= c->dhi) ? 2 : 1;
+        ra.d0 = d;
         ra.recursion = recursion ? 1 : 0;
         ra.presummed = 1;
         ra.nb0 = c->red[i0].nblocks;
@@ -704,13 +754,13 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
             ra.nords = 1;
             ra.nbtot = ra.nb0;
         }
-        int lds = recursion ? c->red[i0].lds_elems : 0;
-        if (recursion && ra.nords == 2) lds = std::max(lds, c->red[i0 + 1].lds_elems);
+        const int lds = red_lds_layout(&c->red[i0], ra.nords, recursion, ra);
         HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(ra, 1, lds, s); }));
         if (!recursion) {
             for (int dd = d + 1; dd <= c->dhi; ++dd) {
                 RedArgs rb = ra;
                 rb.ords = red_d + (dd - c->dlo);
+                rb.d0 = dd;
                 rb.nb0 = rb.nbtot = c->red[dd - c->dlo].nblocks;
                 HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(rb, 1, 0, s); }));
             }
@@ -906,6 +956,61 @@ cum_status cum_plan_check(int n, int d, int b) {
             prev = T[i][k];
         }
         if (r != (int64_t)i * be) return fail(CUM_EINVAL, "d=%d: rank table gives %lld for tuple %zu", d, (long long)r, i);
+    }
+    // recursion tables: every partition splits the d positions into >= 2
+    // disjoint parts of >= 2 positions, no partition twice, and as many as
+    // there are (a(d) - 1, a(n) = sum_k C(n-1, k) a(n-1-k) counting the set
+    // partitions without singletons by the part holding the first element)
+    if (d >= 4) {
+        const int per = d / 2;
+        std::vector<int64_t> a(d + 1, 0);
+        a[0] = 1;
+        for (int m = 1; m <= d; ++m)
+            for (int k = 1; k <= m - 1; ++k) a[m] += binom(m - 1, k) * a[m - 1 - k];
+        if (o.npart != a[d] - 1) return fail(CUM_EINVAL, "d=%d: %d partitions, expected %lld", d, o.npart, (long long)(a[d] - 1));
+        std::set<std::vector<int>> seen;
+        for (int z = 0; z < o.npart; ++z) {
+            std::vector<int> masks;
+            unsigned cover = 0;
+            for (int k = 0; k < per; ++k) {
+                const int32_t v = o.parts[(size_t)z * per + k];
+                if (!v) break;
+                const unsigned mask = (unsigned)v & 1023u;
+                const int where = v >> 10, m = __builtin_popcount(mask);
+                if (m < 2 || m > d - 2 || (cover & mask)) return fail(CUM_EINVAL, "d=%d: bad part in partition %d", d, z);
+                cover |= mask;
+                masks.push_back((int)mask);
+                // where: the staged sub-block's first slot, or the position set's index
+                const size_t si = (size_t)(std::find(o.smask.begin(), o.smask.end(), (uint16_t)mask) - o.smask.begin());
+                if (si >= o.smask.size()) return fail(CUM_EINVAL, "d=%d: part set missing from the set list", d);
+                if (o.lds_elems) {
+                    if (where < 0 || where >= o.lds_elems || (o.gmap[(size_t)where] & 1023) != (int32_t)si ||
+                        (o.gmap[(size_t)where] >> 10) != 0)
+                        return fail(CUM_EINVAL, "d=%d: staged offset of part %d of partition %d", d, k, z);
+                } else if (where != (int)si) {
+                    return fail(CUM_EINVAL, "d=%d: set index of part %d of partition %d", d, k, z);
+                }
+            }
+            if (masks.size() < 2 || cover != (1u << d) - 1u)
+                return fail(CUM_EINVAL, "d=%d: partition %d does not cover the positions", d, z);
+            std::sort(masks.begin(), masks.end());
+            if (!seen.insert(masks).second) return fail(CUM_EINVAL, "d=%d: partition %d repeated", d, z);
+        }
+        // staged slots: each set's sub-block in order, grouped by set size
+        if (o.lds_elems) {
+            size_t e = 0;
+            for (int m = 2; m <= d - 2; ++m) {
+                if (o.mstart[m - 2] != (int32_t)e) return fail(CUM_EINVAL, "d=%d: size-%d segment start", d, m);
+                for (size_t si = 0; si < o.smask.size(); ++si) {
+                    if (__builtin_popcount(o.smask[si]) != m) continue;
+                    for (int64_t f = 0; f < ipow64(b, m); ++f, ++e)
+                        if (e >= o.gmap.size() || o.gmap[e] != (int32_t)(si | (f << 10)))
+                            return fail(CUM_EINVAL, "d=%d: gather map slot %zu", d, e);
+                }
+            }
+            if (o.mstart[d - 3] != (int32_t)e || e != o.gmap.size() || (int)e != o.lds_elems)
+                return fail(CUM_EINVAL, "d=%d: staged slot count", d);
+        }
     }
     for (int shape : {TS_1x1, TS_1x2}) {
         const int wn = shape_wn(shape);
@@ -1288,13 +1393,13 @@ static cum_status batch_enqueue(cum_batch &p, hipStream_t s) {
         const int i0 = d - 2;
         ra.ords = red_d + i0;
         ra.nords = (d + 1 <= p.d_max) ? 2 : 1;
+        ra.d0 = d;
         ra.recursion = 1;
         ra.presummed = 1;
         ra.nb0 = p.red[i0].nblocks;
         ra.nbtot = ra.nb0 + (ra.nords == 2 ? p.red[i0 + 1].nblocks : 0);
         ra.sets = (const SetRed *)p.setred_d.p;
-        int lds = p.red[i0].lds_elems;
-        if (ra.nords == 2) lds = std::max(lds, p.red[i0 + 1].lds_elems);
+        const int lds = red_lds_layout(&p.red[i0], ra.nords, true, ra);
         HIP_TRY(launch_reduce(ra, p.nsets, lds, s));
     }
     return CUM_OK;
@@ -1321,6 +1426,8 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
     int64_t off = 0;
     for (int d = 2; d <= d_max; ++d) {
         OrderPlan *o;
+        if (ipow64(b, d) > INT32_MAX)
+            return fail(CUM_EUNSUPPORTED, "blocks of b^d = %d^%d entries (2^31 or more) are not supported", b, d);
         if ((st = get_order(n, b, d, &o)) || (st = upload_order(*o))) return st;
         p->orders.push_back(o);
         p->out_off.push_back(off);

@@ -427,21 +427,35 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
             for (int kk = 0; kk < KT; kk += STEP) {
                 if constexpr (!BF) {
                     typedef typename std::conditional<PREC == P_F64, d2, f4>::type V;
+                    // every factor of the step is read before any is used, so the
+                    // reads are in flight together
+                    V fa[2][P], fb[WN][2][Q];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int q = 0; q < P; ++q) fa[h][q] = *reinterpret_cast<const V *>(xb + roff[h][q] + kk);
+#pragma unroll
+                    for (int j = 0; j < WN; ++j)
+#pragma unroll
+                        for (int g = 0; g < 2; ++g)
+#pragma unroll
+                            for (int q = 0; q < Q; ++q)
+                                fb[j][g][q] = *reinterpret_cast<const V *>(xb + coff[j][g][q] + kk);
                     V A[2], B[WN][2];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        V v = *reinterpret_cast<const V *>(xb + roff[h][0] + kk);
+                        V v = fa[h][0];
 #pragma unroll
-                        for (int q = 1; q < P; ++q) v *= *reinterpret_cast<const V *>(xb + roff[h][q] + kk);
+                        for (int q = 1; q < P; ++q) v *= fa[h][q];
                         A[h] = v;
                     }
 #pragma unroll
                     for (int j = 0; j < WN; ++j)
 #pragma unroll
                         for (int g = 0; g < 2; ++g) {
-                            V v = *reinterpret_cast<const V *>(xb + coff[j][g][0] + kk);
+                            V v = fb[j][g][0];
 #pragma unroll
-                            for (int q = 1; q < Q; ++q) v *= *reinterpret_cast<const V *>(xb + coff[j][g][q] + kk);
+                            for (int q = 1; q < Q; ++q) v *= fb[j][g][q];
                             B[j][g] = v;
                         }
 #pragma unroll
@@ -671,93 +685,149 @@ hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int
 }
 
 // ---------------------------------------------------------------------------
-// Chunk reduction fused with the cumulant recursion (Alg. 3's reduce; Alg. 4
-// and Alg. 5; eq. cum_r of Section 3.2).  One work-group per stored block j
-// of one dataset: the block's sub-tuples j_S (S = a set of 2..d-2 positions,
-// sorted because j is) get their lower-order block offsets once, in LDS;
-// then each entry sums its chunk partials in chunk order, divides by t, and
-// subtracts the sum over partitions of products of lower cumulants read at
-// (j_S, i_S).  All FP64.
+// Finalisation: M_d = S_d / t and the cumulant recursion (Alg. 4 and Alg. 5;
+// eq. cum_r of Section 3.2), all FP64.  One work-group per stored block j of
+// one dataset.  Per block: the block tuple, the lower-order block offset of
+// every sub-tuple j_S (S = a set of 2..d-2 positions; j_S is sorted because
+// j is) and, when they fit, those lower-order sub-blocks, all in LDS.  Then
+// each entry reads its chunk sum, divides by t and subtracts the sum over
+// partitions of products of lower cumulants read at (j_S, i_S).  Each thread
+// takes EPT entries at a time, so that one read of a partition's parts
+// serves all of them.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
-    __shared__ int64_t base[1 << MAXD];
-    __shared__ int tup[MAXD];
-    __shared__ double *kap[MAXD - 1];
-    extern __shared__ double sub[];  // staged lower-order sub-blocks of the current block
+// Binomial coefficients C(a, r), a < MAXN + MAXD + 1, r <= MAXD, built at
+// compile time (Pascal's rule).
+struct BinomTable {
+    int64_t c[MAXN + MAXD + 1][MAXD + 1];
+};
+constexpr BinomTable make_binom_table() {
+    BinomTable t{};
+    for (int a = 0; a <= MAXN + MAXD; ++a)
+        for (int r = 0; r <= MAXD; ++r)
+            t.c[a][r] = r == 0 ? 1 : (a == 0 ? 0 : t.c[a - 1][r - 1] + t.c[a - 1][r]);
+    return t;
+}
+__constant__ BinomTable c_binom = make_binom_table();
+
+constexpr int EPT = 4;
+
+// Pointers read from memory are generic; these say which ones address
+// global memory, so that their accesses are global (not flat) instructions.
+#define CUM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ CUM_GLOBAL T *gmem(T *p) {
+    return (CUM_GLOBAL T *)p;
+}
+
+// kappa[m - 2] for a wave-uniform m, by constant indices (no dynamic
+// indexing of the record)
+__device__ __forceinline__ double *kappa_of(const SetRed &sr, int m) {
+    switch (m) {
+        case 2: return sr.kappa[0];
+        case 3: return sr.kappa[1];
+        case 4: return sr.kappa[2];
+        case 5: return sr.kappa[3];
+        case 6: return sr.kappa[4];
+        case 7: return sr.kappa[5];
+        default: return sr.kappa[6];
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder &ro, const SetRed &sr, int64_t B,
+                                               char *dyn, int *tup) {
+    constexpr int PARTS = D / 2;  // parts per partition slot
     const int tid = threadIdx.x;
-    const SetRed sr = a.sets ? a.sets[blockIdx.y] : a.set0;
+    const unsigned b = (unsigned)ro.b;
+    unsigned be = 1;
 #pragma unroll
-    for (int k = 0; k < MAXD - 1; ++k)
-        if (tid == k) kap[k] = sr.kappa[k];
-    const double *partial = sr.partial;
+    for (int k = 0; k < D; ++k) be *= b;
+    const bool rec = a.recursion && D >= 4;
+    const bool staged = rec && ro.lds_elems > 0;
+    double *sub = reinterpret_cast<double *>(dyn);
+    int64_t *base = reinterpret_cast<int64_t *>(dyn + a.base_off);
+    int32_t *parts_l = reinterpret_cast<int32_t *>(dyn + a.parts_off);
+    const bool parts_in_lds = rec && a.parts_lds;
+    const CUM_GLOBAL int32_t *parts_g = gmem(ro.parts);
+    const CUM_GLOBAL int64_t *prank = gmem(ro.prank);
+
+    __syncthreads();  // the previous block's readers are done with the LDS tables
+    if (tid < D) tup[tid] = gmem(ro.tuples)[B * D + tid];
+    if (parts_in_lds)
+        for (int i = tid; i < ro.npart * PARTS; i += 256) parts_l[i] = parts_g[i];
+    __syncthreads();
+    if (rec) {
+        // block offset of j_S in the order-|S| layout: the rank of the sorted
+        // tuple j_S (sum of the hockey-stick rank terms) times b^|S|
+        for (int s = tid; s < ro.ns; s += 256) {
+            const unsigned mask = gmem(ro.smask)[s];
+            const int m = __popc(mask);
+            int64_t rank = 0, bm = 1;
+            int prev = 0, k2 = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (mask >> k & 1u) {
+                    rank += c_binom.c[ro.nbar - prev + m - k2 - 1][m - k2] -
+                            c_binom.c[ro.nbar - tup[k] + m - k2 - 1][m - k2];
+                    prev = tup[k];
+                    ++k2;
+                    bm *= b;
+                }
+            base[s] = rank * bm;
+        }
+        __syncthreads();
+    }
+    if (staged) {
+        // the block's lower-order sub-blocks into LDS, by size of S (the
+        // cumulant array of each size is a separate buffer)
+#pragma unroll
+        for (int m = 2; m <= D - 2; ++m) {
+            const CUM_GLOBAL double *kp = gmem(sr.kappa[m - 2]);
+            for (int e = ro.mstart[m - 2] + tid; e < ro.mstart[m - 1]; e += 256) {
+                const int g = gmem(ro.gmap)[e];
+                sub[e] = kp[base[g & 1023] + (g >> 10)];
+            }
+        }
+        __syncthreads();
+    }
+
+    CUM_GLOBAL double *out = gmem(sr.kappa[D - 2]);
+    const CUM_GLOBAL double *partial = gmem(sr.partial + ro.out_off);
     const int64_t stride = sr.stride, nchunks = a.presummed ? 1 : sr.nchunks;
     const double tt = (double)sr.t;
-    for (int64_t gb = blockIdx.x; gb < a.nbtot; gb += gridDim.x) {
-        const int oi = gb < a.nb0 ? 0 : 1;
-        const int64_t B = oi ? gb - a.nb0 : gb;
-        const RedOrder ro = a.ords[oi];
-        const int d = ro.d, b = ro.b;
-        const int64_t be = ipow_dev(b, d);
-        const bool rec = a.recursion && d >= 4;
-        const bool staged = rec && ro.loff != nullptr;
-        __syncthreads();
-        if (tid < d) tup[tid] = ro.tuples[B * d + tid];
-        __syncthreads();
-        if (rec) {
-            for (int mask = tid; mask < (1 << d); mask += 256) {
-                const int m = __popc(mask);
-                if (m < 2 || m > d - 2) continue;
-                int u[MAXD], mm = 0;
+    // The partial sums are either in this layout (one per stored copy) or in
+    // the layout of block size pb, which holds each sorted variable tuple
+    // once; then every stored copy reads that tuple's sums.
+    const bool canon = ro.pb != ro.b;
+    bool need_sort = false;  // equal adjacent blocks: the variables need sorting
 #pragma unroll
-                for (int k = 0; k < MAXD; ++k)
-                    if (k < d && (mask >> k & 1)) u[mm++] = tup[k];
-                base[mask] = rank_sorted(u, m, ro.nbar) * ipow_dev(b, m);
-            }
-        }
-        __syncthreads();
-        if (staged) {
-            // the block's sub-blocks j_S of every position set S, into LDS
-            for (int mask = 0; mask < (1 << d); ++mask) {
-                const int off = ro.loff[mask];
-                if (off < 0) continue;
-                const int m = __popc(mask);
-                const int sz = (int)ipow_dev(b, m);
-                const double *srcp = kap[m - 2] + base[mask];
-                for (int e = tid; e < sz; e += 256) sub[off + e] = srcp[e];
-            }
-            __syncthreads();
-        }
-        double *out = kap[d - 2];
-        // The partial sums are either in this layout (one per stored copy) or
-        // in the layout of block size pb, which holds each sorted variable
-        // tuple once; then every stored copy reads that tuple's sums.
-        const bool canon = ro.pb != b;
-        bool need_sort = false;  // equal adjacent blocks: the variables need sorting
-        for (int k = 0; k + 1 < d; ++k) need_sort |= tup[k] == tup[k + 1];
-        for (int64_t o = tid; o < be; o += 256) {
-            const int64_t e = B * be + o;
-            int r[MAXD];  // in-block digits, first position most significant
-            if (rec || canon) {
-                int64_t oo = o;
+    for (int k = 0; k + 1 < D; ++k) need_sort |= tup[k] == tup[k + 1];
+
+    for (unsigned o0 = tid; o0 < be; o0 += 256 * EPT) {
+        int r[EPT][D];  // in-block digits, first position most significant
+        double M[EPT];
 #pragma unroll
-                for (int k = MAXD - 1; k >= 0; --k)
-                    if (k < d) {
-                        r[k] = (int)(oo % b);
-                        oo /= b;
-                    }
-            }
-            int64_t poff = e;
-            bool pad = false;
-            if (canon) {
-                int u[MAXD];
+        for (int q = 0; q < EPT; ++q) {
+            unsigned oo = o0 + 256u * q;
+            const bool valid = oo < be;
+            if (!valid) oo = 0;
 #pragma unroll
-                for (int k = 0; k < MAXD; ++k) u[k] = k < d ? tup[k] * b + r[k] : INT_MAX;
+            for (int k = D - 1; k >= 0; --k) {
+                r[q][k] = (int)(oo % b);
+                oo /= b;
+            }
+            int64_t poff = (int64_t)B * be + o0 + 256u * q;
+            bool pad = !valid;
+            if (canon && valid) {
+                int u[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) u[k] = tup[k] * ro.b + r[q][k];
                 if (need_sort) {
-                    // odd-even transposition network: MAXD rounds sort MAXD keys
+                    // odd-even transposition network: D rounds sort D keys
 #pragma unroll
-                    for (int rd = 0; rd < MAXD; ++rd)
+                    for (int rd = 0; rd < D; ++rd)
 #pragma unroll
-                        for (int k = rd & 1; k + 1 < MAXD; k += 2) {
+                        for (int k = rd & 1; k + 1 < D; k += 2) {
                             const int lo = min(u[k], u[k + 1]), hi = max(u[k], u[k + 1]);
                             u[k] = lo;
                             u[k + 1] = hi;
@@ -765,61 +835,110 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
                 }
                 int umax = 0;
 #pragma unroll
-                for (int k = 0; k < MAXD; ++k)
-                    if (k < d) umax = max(umax, u[k]);
+                for (int k = 0; k < D; ++k) umax = max(umax, u[k]);
                 pad = umax >= ro.n;  // a padded position of a ragged block: M = 0
                 if (!pad) {
                     const int pb = ro.pb, w = ro.pnbar + 1;
                     int64_t rank = 0, in = 0;
                     int prev = 0;
 #pragma unroll
-                    for (int k = 0; k < MAXD; ++k)
-                        if (k < d) {
-                            const int jb = pb == 1 ? u[k] : u[k] / pb;
-                            rank += ro.prank[k * w + prev] - ro.prank[k * w + jb];
-                            in = in * pb + (u[k] - jb * pb);
-                            prev = jb;
-                        }
+                    for (int k = 0; k < D; ++k) {
+                        const int jb = pb == 1 ? u[k] : u[k] / pb;
+                        rank += prank[k * w + prev] - prank[k * w + jb];
+                        in = in * pb + (u[k] - jb * pb);
+                        prev = jb;
+                    }
                     poff = rank + in;
                 }
             }
             double S = 0.0;
             if (!pad) {
-                const double *pp = partial + ro.out_off + poff;
+                const CUM_GLOBAL double *pp = partial + poff;
                 int64_t c = 0;
                 // eight independent loads in flight, summed in chunk order
                 for (; c + 8 <= nchunks; c += 8) {
                     double v[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) v[q] = pp[(c + q) * stride];
+                    for (int x = 0; x < 8; ++x) v[x] = pp[(c + x) * stride];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) S += v[q];
+                    for (int x = 0; x < 8; ++x) S += v[x];
                 }
                 for (; c < nchunks; ++c) S += pp[c * stride];
             }
-            const double M = S / tt;
-            double res = M;
-            if (rec) {
-                double sum = 0.0;
-                for (int z = 0; z < ro.npart; ++z) {
-                    double prod = 1.0;
-#pragma unroll
-                    for (int pt = 0; pt < MAXPARTS; ++pt) {
-                        const int mask = ro.parts[z * MAXPARTS + pt];
-                        if (!mask) break;
-                        int flat = 0;
-#pragma unroll
-                        for (int k = 0; k < MAXD; ++k)
-                            if (k < d && (mask >> k & 1)) flat = flat * b + r[k];
-                        prod *= staged ? sub[ro.loff[mask] + flat] : kap[__popc(mask) - 2][base[mask] + flat];
-                    }
-                    sum += prod;
-                }
-                res = M - sum;
-            }
-            out[e] = res;
+            M[q] = S / tt;
         }
-        if (sr.stamp && tid == 0) atomicMax(sr.stamp, (unsigned long long)wall_clock64());
+        // sum over partitions of products of lower cumulants; the lower-order
+        // sub-blocks are in LDS (staged) or read from memory
+        auto recursion = [&](auto staged_t) {
+            constexpr bool ST = decltype(staged_t)::value;
+            double sum[EPT];
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) sum[q] = 0.0;
+            for (int z = 0; z < ro.npart; ++z) {
+                double prod[EPT];
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) prod[q] = 1.0;
+#pragma unroll
+                for (int pt = 0; pt < PARTS; ++pt) {
+                    // the same part for every lane: make that explicit, so that the
+                    // position tests below are scalar
+                    const int pk = __builtin_amdgcn_readfirstlane(parts_in_lds ? parts_l[z * PARTS + pt]
+                                                                               : parts_g[z * PARTS + pt]);
+                    if (!pk) break;
+                    const unsigned mask = (unsigned)pk & 1023u;
+                    const int where = pk >> 10;
+                    int flat[EPT];
+#pragma unroll
+                    for (int q = 0; q < EPT; ++q) {
+                        flat[q] = 0;
+#pragma unroll
+                        for (int k = 0; k < D; ++k)
+                            if (mask >> k & 1u) flat[q] = flat[q] * (int)b + r[q][k];
+                    }
+                    if constexpr (ST) {
+#pragma unroll
+                        for (int q = 0; q < EPT; ++q) prod[q] *= sub[where + flat[q]];
+                    } else {
+                        const CUM_GLOBAL double *src = gmem(kappa_of(sr, __popc(mask))) + base[where];
+#pragma unroll
+                        for (int q = 0; q < EPT; ++q) prod[q] *= src[flat[q]];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) sum[q] += prod[q];
+            }
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) M[q] -= sum[q];
+        };
+        if (staged)
+            recursion(std::true_type());
+        else if (rec)
+            recursion(std::false_type());
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const unsigned o = o0 + 256u * q;
+            if (o < be) out[B * be + o] = M[q];
+        }
+    }
+    if (sr.stamp && tid == 0) atomicMax(sr.stamp, (unsigned long long)wall_clock64());
+}
+
+template <int D0>
+__global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
+    extern __shared__ __align__(16) char dyn[];
+    __shared__ int tup[MAXD];
+    SetRed sr = a.set0;
+    if (a.sets) sr = a.sets[blockIdx.y];
+    for (int64_t gb = blockIdx.x; gb < a.nbtot; gb += gridDim.x) {
+        if (gb < a.nb0) {
+            const RedOrder ro = a.ords[0];
+            finalize_block<D0>(a, ro, sr, gb, dyn, tup);
+        } else {
+            if constexpr (D0 < MAXD) {
+                const RedOrder ro = a.ords[1];
+                finalize_block<D0 + 1>(a, ro, sr, gb - a.nb0, dyn, tup);
+            }
+        }
     }
 }
 
@@ -855,10 +974,22 @@ hipError_t launch_chunksum(const SetRed *sets, const SetRed &set0, int nsets, in
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_doubles, hipStream_t s) {
+hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, hipStream_t s) {
     int64_t gx = a.nbtot;
     if (gx > 65535) gx = 65535;
-    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)gx, (unsigned)nsets), dim3(256), (size_t)lds_doubles * 8, s, a);
+    const dim3 grid((unsigned)gx, (unsigned)nsets), block(256);
+    switch (a.d0) {
+        case 2: hipLaunchKernelGGL(reduce_kernel<2>, grid, block, (size_t)lds_bytes, s, a); break;
+        case 3: hipLaunchKernelGGL(reduce_kernel<3>, grid, block, (size_t)lds_bytes, s, a); break;
+        case 4: hipLaunchKernelGGL(reduce_kernel<4>, grid, block, (size_t)lds_bytes, s, a); break;
+        case 5: hipLaunchKernelGGL(reduce_kernel<5>, grid, block, (size_t)lds_bytes, s, a); break;
+        case 6: hipLaunchKernelGGL(reduce_kernel<6>, grid, block, (size_t)lds_bytes, s, a); break;
+        case 7: hipLaunchKernelGGL(reduce_kernel<7>, grid, block, (size_t)lds_bytes, s, a); break;
+        case 8: hipLaunchKernelGGL(reduce_kernel<8>, grid, block, (size_t)lds_bytes, s, a); break;
+        case 9: hipLaunchKernelGGL(reduce_kernel<9>, grid, block, (size_t)lds_bytes, s, a); break;
+        case 10: hipLaunchKernelGGL(reduce_kernel<10>, grid, block, (size_t)lds_bytes, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

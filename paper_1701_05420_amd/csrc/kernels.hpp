@@ -21,10 +21,15 @@ struct MomentArgs {
 };
 
 struct RedArgs {
-    const RedOrder *ords;  // the orders finalised by this launch (1 or 2)
+    const RedOrder *ords;  // the orders finalised by this launch (1 or 2: orders d0 and d0 + 1)
     int32_t nords;
+    int32_t d0;         // order of ords[0]
     int32_t recursion;  // 0: plain moments (no cumulant recursion)
     int32_t presummed;  // 1: chunk 0 of the partial sums already holds their sum
+    int32_t base_off;   // dynamic LDS layout: staged sub-blocks at 0, the block's
+    int32_t parts_off;  // lower-order offsets at base_off, the partition table at
+    int32_t parts_lds;  // parts_off when parts_lds (else it is read from memory)
+    int32_t pad;
     int64_t nb0;   // blocks of the first order
     int64_t nbtot; // blocks of all orders of the launch
     const SetRed *sets;  // per-dataset records (grid.y), or null: set0
@@ -39,7 +44,7 @@ int lds_bytes_moment(int prec, int n);
 hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xst, int prec,
                         bool center, bool in_f64, hipStream_t s);
 hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s);
-hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_doubles, hipStream_t s);
+hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, hipStream_t s);
 hipError_t launch_chunksum(const SetRed *sets, const SetRed &set0, int nsets, int64_t entries, hipStream_t s);
 hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,
                          hipStream_t s);

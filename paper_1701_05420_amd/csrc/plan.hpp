@@ -108,18 +108,23 @@ struct SetDev {
 // Reduction / recursion records.
 constexpr int MAXPARTS = MAXD / 2;  // parts of size >= 2 in a partition of <= MAXD positions
 struct RedOrder {
-    const uint8_t *tuples;  // nblocks x d sorted block tuples (lexicographic order)
-    const uint16_t *parts;  // npart x MAXPARTS position masks (0 = unused)
-    const int32_t *loff;    // 2^d: LDS offset of the staged sub-block of each position
-                            // mask of 2..d-2 positions (null: read them from memory)
-    const int64_t *prank;   // d x (pnbar + 1) rank terms of the partial-sum layout:
-                            // prank[k][x] = pb^d * C(pnbar - x + d - k - 1, d - k)
+    const uint8_t *tuples;   // nblocks x d sorted block tuples (lexicographic order)
+    const int32_t *parts;    // npart x (d/2) parts, packed mask | where << 10 (0 = no more parts);
+                             // where = LDS offset of the staged sub-block (staged orders) or
+                             // the index of the part's position set in smask (others)
+    const uint16_t *smask;   // ns position sets S of 2..d-2 positions, by size then value
+    const int32_t *gmap;     // lds_elems staged slots: s | flat << 10, grouped by |S|
+    const int64_t *prank;    // d x (pnbar + 1) rank terms of the partial-sum layout:
+                             // prank[k][x] = pb^d * C(pnbar - x + d - k - 1, d - k)
     int64_t nblocks;
-    int64_t out_off;        // offset of this order in the per-chunk partial vector
+    int64_t out_off;         // offset of this order in the per-chunk partial vector
     int32_t d, npart, nbar, b;
-    int32_t lds_elems;      // doubles staged per block (0 without staging)
-    int32_t pb, pnbar;      // block size and blocks per mode of the partial-sum layout
-    int32_t n;              // variables
+    int32_t ns;              // position sets of 2..d-2 positions
+    int32_t lds_elems;       // doubles staged per block (0: lower orders read from memory)
+    int32_t mstart[MAXD];    // staged slots of sets of size m start at mstart[m - 2]; mstart[d - 3] = lds_elems
+    int32_t pb, pnbar;       // block size and blocks per mode of the partial-sum layout
+    int32_t n;               // variables
+    int32_t pad;
 };
 constexpr int RED_LDS_MAX = 6144;  // doubles of lower-order sub-blocks staged per block (48 KiB)
 
