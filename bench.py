@@ -69,7 +69,16 @@ def time_path(torch, pc, Xd, d_max, b, prec, steps, warmup, tune):
     kinds = pc.timing_read()
     pc.timing_enable(False)
     torch.cuda.synchronize()
-    return wall, kinds, out, tuned
+    # third pass: one pair of events around each step, for the spread
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in evs:
+        e0.record()
+        pc.cumulants(Xd, d_max, b, prec, ws=ws, out=out)
+        e1.record()
+    torch.cuda.synchronize()
+    per_step = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    pct = {f"p{q}": float(np.percentile(per_step, q)) for q in (10, 50, 90)}
+    return wall, kinds, out, tuned, pct
 
 
 def sampled_errors(orc, pc, X, kappa, n, d_max, b, count=300, seed=7):
@@ -93,9 +102,18 @@ def sampled_errors(orc, pc, X, kappa, n, d_max, b, count=300, seed=7):
     return errs
 
 
-def cpu_baseline(orc, X, n, d_max, b, pc, target_s):
-    """The FP64 oracle (dense over all n^d entries) on the first ts samples,
-    ts sized for about target_s seconds; reported in the benchmark's unit."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_rate(orc, X, n, d_max, b, pc, target_s):
+    """Oracle on the first ts samples, ts sized for about target_s seconds."""
     ts = 64
     t0 = time.perf_counter()
     orc.cumulants_dense(X[:ts], d_max)
@@ -104,11 +122,24 @@ def cpu_baseline(orc, X, n, d_max, b, pc, target_s):
     t0 = time.perf_counter()
     orc.cumulants_dense(X[:ts], d_max)
     dt = time.perf_counter() - t0
-    flops = alg_flops(pc, ts, n, d_max, b)
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": orc.max_threads(), "kind": "oracle",
+    return alg_flops(pc, ts, n, d_max, b) / dt / 1e12, ts, dt
+
+
+def cpu_baseline(orc, X, n, d_max, b, pc, target_s):
+    """The FP64 oracle (dense over all n^d entries) on a leading slice of the
+    samples, with every host thread and with one; in the benchmark's unit."""
+    cores = orc.max_threads()
+    value, ts, dt = _oracle_rate(orc, X, n, d_max, b, pc, target_s)
+    orc.set_threads(1)
+    try:
+        v1, ts1, dt1 = _oracle_rate(orc, X, n, d_max, b, pc, target_s / 3)
+    finally:
+        orc.set_threads(cores)
+    return {"value": value, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
             "sample": f"first {ts} of {len(X)} samples, dense FP64 oracle over all n^d entries of orders 2..{d_max}, "
                       f"{dt:.1f} s; effective FLOP counted as for the GPU (2 t sum_d stored_d)",
-            "seconds": dt}
+            "seconds": dt, "cpu_model": cpu_model(),
+            "single_thread": {"value": v1, "sample": f"first {ts1} samples, {dt1:.1f} s"}}
 
 
 def bench_batched(torch, pc, prec, steps, warmup, tune):
@@ -235,13 +266,14 @@ def main():
     res, kappa = {}, {}
     for p in precs:
         log(f"timing {p}")
-        wall, kinds, out, tuned = time_path(torch, pc, Xd, d_max, b, p, args.steps, args.warmup, not args.no_tune)
+        wall, kinds, out, tuned, pct = time_path(torch, pc, Xd, d_max, b, p, args.steps, args.warmup,
+                                                 not args.no_tune)
         mom_ms, mom_n = kinds["moment"]
         per_launch = mom_ms / max(mom_n, 1)
         cfg = pc.get_tuning(t, n, d_max, b, p)
         kflops = alg_flops(pc, t, n, d_max, cfg["inner_b"])  # entries the contraction sums
         achieved = kflops / (per_launch * 1e-3) / 1e12
-        res[p] = {"ms_per_step": wall * 1e3, "tflops": flops / wall / 1e12,
+        res[p] = {"ms_per_step": wall * 1e3, "tflops": flops / wall / 1e12, "ms_per_step_pct": pct,
                   "tflops_unique": uflops / wall / 1e12,
                   "moment_ms_per_launch": per_launch, "moment_tflops": achieved,
                   "moment_flop_per_launch": kflops,
