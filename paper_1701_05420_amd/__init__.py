@@ -138,7 +138,7 @@ def get_tuning(t: int, n: int, d_max: int, b: int, prec) -> dict:
     return {"shape": out.shape, "target_items": out.target_items, "inner_b": out.inner_b}
 
 
-def set_tuning(t: int, n: int, d_max: int, b: int, prec, shape=None, target_items=1024, inner_b=1) -> None:
+def set_tuning(t: int, n: int, d_max: int, b: int, prec, shape=None, target_items=4096, inner_b=1) -> None:
     """Fix the configuration for a shape (shape=None forgets it)."""
     if shape is None:
         _check(_lib.cum_set_tuning(t, n, d_max, b, _prec(prec), None))

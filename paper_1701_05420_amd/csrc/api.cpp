@@ -559,7 +559,7 @@ static void save_tune_file() {
 }
 
 static int default_shape(int prec) { return prec == P_F32 ? TS_1x1 : TS_1x2; }
-constexpr int DEFAULT_TARGET = 1024;
+constexpr int DEFAULT_TARGET = 4096;
 // The contraction computes each distinct sorted variable tuple once (inner
 // block size 1) unless tuning chose otherwise.
 static int default_inner(int) { return 1; }
@@ -604,8 +604,8 @@ static cum_status get_call_cfg(int n, int b, int bi, int dlo, int dhi, int prec,
     // expensive tiles first, so that the tail of each XCD's queue is short
     std::stable_sort(tiles.begin(), tiles.end(), [](const HostTile &x, const HostTile &y) { return x.cost > y.cost; });
     const int64_t ntiles = (int64_t)tiles.size();
-    // sample chunks (whole stages): about `target` work items (1024 fills the
-    // 256 CUs twice over with two work-groups each), chunks of >= 4 stages
+    // sample chunks (whole stages): about `target` work items (1024 fill the
+    // 256 CUs' four work-group slots once), chunks of >= 4 stages
     int64_t want = (target + ntiles - 1) / ntiles;
     int64_t maxch = std::max<int64_t>(1, c->nstages / 4);
     int64_t nch = std::max<int64_t>(1, std::min(want, maxch));
@@ -1117,7 +1117,7 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     std::lock_guard<std::mutex> lk(g_mu);
     hipStream_t s = (hipStream_t)stream;
     const int shapes[] = {TS_1x1, TS_1x2};
-    const int targets[] = {512, 1024, 2048, 4096};
+    const int targets[] = {1024, 2048, 4096, 8192, 16384};
     std::vector<CallPlan *> cands;
     std::vector<int> cand_target;
     size_t part_max = 0;

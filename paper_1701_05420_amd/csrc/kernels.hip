@@ -458,15 +458,17 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                             for (int q = 1; q < Q; ++q) v *= fb[j][g][q];
                             B[j][g] = v;
                         }
+                    // each accumulator's products of the step back to back (the
+                    // scheduling barrier keeps the compiler from interleaving them)
 #pragma unroll
-                    for (int u = 0; u < VEC; ++u)
+                    for (int j = 0; j < WN; ++j)
 #pragma unroll
-                        for (int j = 0; j < WN; ++j)
+                        for (int h = 0; h < 2; ++h)
 #pragma unroll
-                            for (int h = 0; h < 2; ++h)
+                            for (int g = 0; g < 2; ++g) {
+                                if (all || (vmask >> (j * 4 + h * 2 + g) & 1u)) {
 #pragma unroll
-                                for (int g = 0; g < 2; ++g)
-                                    if (all || (vmask >> (j * 4 + h * 2 + g) & 1u)) {
+                                    for (int u = 0; u < VEC; ++u) {
                                         if constexpr (PREC == P_F64)
                                             acc64[j][h][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(
                                                 A[h][u], B[j][g][u], acc64[j][h][g], 0, 0, 0);
@@ -474,6 +476,9 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                                             acc[j][h][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                                                 A[h][u], B[j][g][u], acc[j][h][g], 0, 0, 0);
                                     }
+                                }
+                                __builtin_amdgcn_sched_barrier(0);
+                            }
                 } else {
                     bf8 As[2][NS], Bs[WN][2][NS];
 #pragma unroll

@@ -88,13 +88,15 @@ def test_batch_integer_exact_and_autotune(dev, orc):
 
 def test_batch_workload_sampled(dev, orc):
     """The 512-dataset workload (n = 32, b = 4, d <= 4, t_i log-uniform in
-    [500, 20000]) at its full size, FP32 path; sampled datasets checked."""
+    [500, 20000]) at its full size, FP32 path, in the autotuned configuration
+    the benchmark times; sampled datasets checked."""
     torch, pc = dev
     w = workloads.WORKLOADS["batch512-t-corr-n32"]
     Xs = workloads.generate("batch512-t-corr-n32")
     ts = [len(X) for X in Xs]
     Xd = [torch.from_numpy(X).cuda() for X in Xs]
     batch = pc.Batch(ts, w["n"], w["d_max"], w["b"], "f32")
+    say(f"batch512 autotuned: {batch.autotune(Xd)}")
     _, K = batch.run(Xd)
     torch.cuda.synchronize()
     for s in [0, 7, 100, 255, 511]:

@@ -129,7 +129,7 @@ def test_entry_points_validate_before_touching_the_device(pc):
 def test_tuning_round_trip_and_validation(pc):
     shape = (1000, 12, 4, 3, "f32")
     pc.set_tuning(*shape, None)
-    assert pc.get_tuning(*shape) == {"shape": 0, "target_items": 1024, "inner_b": 1}
+    assert pc.get_tuning(*shape) == {"shape": 0, "target_items": 4096, "inner_b": 1}
     pc.set_tuning(*shape, "32x64", 2048, inner_b=3)
     assert pc.get_tuning(*shape) == {"shape": 2, "target_items": 2048, "inner_b": 3}
     for bad in [dict(inner_b=0), dict(inner_b=4), dict(target_items=0)]:
@@ -139,8 +139,9 @@ def test_tuning_round_trip_and_validation(pc):
         pc.set_tuning(*shape, 1, 512)  # no such tile shape
     assert pc.get_tuning(*shape)["target_items"] == 2048  # refused settings change nothing
     pc.set_tuning(*shape, None)
-    # the workspace follows the chosen partial-sum layout
-    pc.set_tuning(100_000, 48, 4, 4, "f32", "32x32", 1024, inner_b=4)
+    # the workspace follows the chosen chunking: more work items, more
+    # sample chunks, a larger partial-sum buffer
+    pc.set_tuning(100_000, 48, 4, 4, "f32", "32x32", 16384, inner_b=1)
     big = pc.workspace_size(100_000, 48, 4, 4, "f32")
     pc.set_tuning(100_000, 48, 4, 4, "f32", "32x32", 1024, inner_b=1)
     small = pc.workspace_size(100_000, 48, 4, 4, "f32")
@@ -167,4 +168,4 @@ def test_tune_file_is_read_and_bad_lines_skipped(tmp_path):
                          timeout=120).stdout.splitlines()
     assert out[0] == "{'shape': 2, 'target_items': 4096, 'inner_b': 2}"
     for line in out[1:]:
-        assert line == "{'shape': 0, 'target_items': 1024, 'inner_b': 1}"
+        assert line == "{'shape': 0, 'target_items': 4096, 'inner_b': 1}"
