@@ -81,9 +81,32 @@ def time_path(torch, pc, Xd, d_max, b, prec, steps, warmup, tune):
     return wall, kinds, out, tuned, pct
 
 
+def diagonal_block_offsets(pc, n, d, b, count, rng):
+    """Stored offsets of random copies in blocks with a repeated block index
+    (where the redundant copies are)."""
+    if d < 2:
+        return np.zeros(0, dtype=np.int64)
+    be, nbar = b ** d, -(-n // b)
+    out = []
+    while len(out) < count:
+        j = np.sort(rng.integers(0, nbar, size=d))
+        k = rng.integers(1, d)
+        j[k] = j[k - 1]
+        i = rng.permutation(j * b + rng.integers(0, b, size=d))
+        if i.max() >= n:
+            continue
+        base = pc.stored_offset(n, d, b, sorted(i.tolist())) // be * be
+        inb = 0
+        for q in np.argsort(i // b, kind="stable"):
+            inb = inb * b + int(i[q] % b)
+        out.append(base + inb)
+    return np.array(out, dtype=np.int64)
+
+
 def sampled_errors(orc, pc, X, kappa, n, d_max, b, count=300, seed=7):
     """e_d = max |gpu - oracle| / max |oracle| over sampled stored entries
-    (random positions plus every pure-diagonal entry)."""
+    (random positions, every pure-diagonal entry, and random copies in
+    blocks with a repeated block index)."""
     _, Xc = orc.center(X)
     errs = {}
     rng = np.random.default_rng(seed)
@@ -91,7 +114,7 @@ def sampled_errors(orc, pc, X, kappa, n, d_max, b, count=300, seed=7):
         elems = pc.layout(n, d, b)["elems"]
         offs = rng.choice(elems, size=min(count, elems), replace=False)
         diag = [pc.stored_offset(n, d, b, [i] * d) for i in range(n)]
-        offs = np.unique(np.concatenate([offs, diag]))
+        offs = np.unique(np.concatenate([offs, diag, diagonal_block_offsets(pc, n, d, b, count // 3, rng)]))
         idx = orc.block_indices(n, d, b, offs)
         keep = idx[:, 0] >= 0
         offs, idx = offs[keep], idx[keep]
@@ -195,6 +218,39 @@ def bench_batched(torch, pc, prec, steps, warmup, tune):
             "tuning": tuned}
 
 
+def bench_workloads(torch, pc, orc, steps, tune):
+    """The higher-order workloads (d_max = 6 and 5), FP32 and FP64 paths:
+    step time, effective and moment-kernel throughput, and e_d per order
+    against the oracle on sampled entries (random positions, every pure
+    diagonal, and entries of blocks with repeated block indices)."""
+    import workloads
+
+    out = {}
+    for name in ["laplace-mix-n24-t200000", "ar1-garch-n64-t50000"]:
+        w = workloads.WORKLOADS[name]
+        n, b, d_max, t = w["n"], w["b"], w["d_max"], w["t"]
+        log(f"workload {name}")
+        X = workloads.generate(name)
+        Xd = torch.from_numpy(X).cuda()
+        flops = alg_flops(pc, t, n, d_max, b)
+        res, kap = {}, {}
+        for p in ["f32", "f64"]:
+            wall, kinds, o, tuned, pct = time_path(torch, pc, Xd, d_max, b, p, steps, 2, tune)
+            cfg = pc.get_tuning(t, n, d_max, b, p)
+            kflops = alg_flops(pc, t, n, d_max, cfg["inner_b"])
+            per_launch = kinds["moment"][0] / max(kinds["moment"][1], 1)
+            res[p] = {"ms_per_step": wall * 1e3, "tflops": flops / wall / 1e12, "ms_per_step_pct": pct,
+                      "moment_tflops": kflops / (per_launch * 1e-3) / 1e12,
+                      "mfma_frac": kflops / (per_launch * 1e-3) / 1e12 / PEAK[p], "config": cfg}
+            kap[p] = {d: o[d].cpu().numpy() for d in o}
+            log(f"  {p}: {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s")
+        errs = sampled_errors(orc, pc, X, kap, n, d_max, b, count=40, seed=11)
+        for p in res:
+            res[p]["rel_err"] = {str(d): errs[d][p] for d in errs}
+        out[name] = {"n": n, "b": b, "d_max": d_max, "t": t, "alg_flop_per_step": flops, "paths": res}
+    return out
+
+
 def traffic_record(prec, workload):
     """HBM bytes per moment launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
@@ -222,6 +278,7 @@ def main():
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (planner defaults)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-dataset batched measurement")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the d_max = 5, 6 workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -320,6 +377,8 @@ def main():
         line["batched"] = bench_batched(torch, pc, main_p, max(3, args.steps // 4), 1, not args.no_tune)
         log(f"  batched: {line['batched']['datasets_per_s']:.0f} datasets/s vs "
             f"{line['batched']['per_dataset_calls']['datasets_per_s']:.0f} with one call per dataset")
+    if not args.no_workloads:
+        line["workloads"] = bench_workloads(torch, pc, orc, max(5, args.steps // 2), not args.no_tune)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(orc, X, n, d_max, b, pc, args.cpu_seconds)

@@ -29,13 +29,38 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def diagonal_block_offsets(pc, n, d, b, count, rng):
+    """Stored offsets in blocks with repeated block indices, where the
+    redundant copies live (random positions, the canonical copy or not)."""
+    L = pc.layout(n, d, b)
+    be, nbar = L["block_elems"], L["nbar"]
+    out = []
+    while len(out) < count:
+        j = np.sort(rng.integers(0, nbar, size=d))
+        k = rng.integers(1, d)
+        j[k] = j[k - 1]  # a repeated block index (j stays sorted)
+        i = j * b + rng.integers(0, b, size=d)
+        if i.max() >= n:
+            continue
+        i = rng.permutation(i)  # any copy: the in-block digits need not be sorted
+        base = pc.stored_offset(n, d, b, sorted(i.tolist())) // be * be
+        dig = [x - (x // b) * b for x in i]
+        # position of this (permuted) copy inside the block of the sorted block tuple
+        order = np.argsort([x // b for x in i], kind="stable")
+        inb = 0
+        for k in order:
+            inb = inb * b + dig[k]
+        out.append(base + inb)
+    return np.array(out, dtype=np.int64)
+
+
 def sampled_check(pc, orc, Xc, K, n, dmax, b, precs, count, seed):
     rng = np.random.default_rng(seed)
     for d in range(2, dmax + 1):
         elems = pc.layout(n, d, b)["elems"]
         offs = rng.choice(elems, size=min(count, elems), replace=False)
         diag = [pc.stored_offset(n, d, b, [i] * d) for i in range(n)]
-        offs = np.unique(np.concatenate([offs, diag]))
+        offs = np.unique(np.concatenate([offs, diag, diagonal_block_offsets(pc, n, d, b, count // 2, rng)]))
         idx = orc.block_indices(n, d, b, offs)
         keep = idx[:, 0] >= 0
         offs, idx = offs[keep], idx[keep]
