@@ -232,6 +232,50 @@ cum_status cum_batch_autotune(cum_batch *plan, const double *const *X_i, cum_tun
 
 cum_status cum_batch_destroy(cum_batch *plan);
 
+/* ------------------------------------------------------------------------
+ * Streaming windows.  Sums over samples are additive over disjoint sample
+ * ranges (the chunk decomposition of Alg. 3, eq. mapred), so the moment sums
+ * of a window of samples are the sums of its batches', and a batch leaves
+ * the window by subtracting its sums.  A stream keeps, in FP64, the sums of
+ * products of the shifted data y = x - c for orders 1..d_max (each sorted
+ * variable tuple once) about a fixed shift c.  Cumulants of the window are
+ * computed on demand: delta = mean(y), central moments by expanding
+ * prod_k (y_k - delta_k) over the subsets of positions (binomial
+ * re-centring), then the recursion of Section 3.2.  The products of each
+ * batch run in prec as in cum_cumulants; the re-centring is exact algebra
+ * in FP64, well conditioned while c stays near the window's mean (the
+ * default shift is the first batch's mean).
+ * ------------------------------------------------------------------------ */
+typedef struct cum_stream cum_stream;
+
+/* Host only (allocates the stream's device memory).  shift (host, n values)
+ * or NULL: the mean of the first batch added becomes the shift. */
+cum_status cum_stream_create(int n, int d_max, int b, cum_prec prec, const double *shift /* host */,
+                             cum_stream **stream_out /* host out */);
+
+/* Add (sign = +1) or remove (sign = -1) the batch X (t x n FP64, ld ldx,
+ * device).  A removed batch must hold samples that were added (the window's
+ * sums are exact sums, so removing what was added restores them up to
+ * rounding).  CUM_EINVAL if the window would hold fewer than 0 samples.
+ * Asynchronous on stream; when a batch is larger than any before, the
+ * stream's workspace grows, which synchronises stream first. */
+cum_status cum_stream_update(cum_stream *s, const double *X, int64_t t, int64_t ldx, int sign, void *stream);
+
+/* The window's mean (device, n doubles, or NULL) and cumulants c_2..c_dmax
+ * in block storage (kappa: host array of d_max-1 device pointers,
+ * kappa[d-2] of cum_layout_query(n, d, b).elems doubles).  CUM_EINVAL if the
+ * window holds no samples.  Asynchronous on stream. */
+cum_status cum_stream_cumulants(cum_stream *s, double *mean, double *const *kappa, void *stream);
+
+/* Host only.  Samples in the window. */
+cum_status cum_stream_count(cum_stream *s, int64_t *t /* host out */);
+
+/* Empty the window (the shift is kept).  Asynchronous on stream. */
+cum_status cum_stream_reset(cum_stream *s, void *stream);
+
+/* Synchronises the device, then frees the stream. */
+cum_status cum_stream_destroy(cum_stream *s);
+
 /* Host only.  Check that the moment-contraction tiling of order d covers
  * every stored entry exactly once and multiplies the variables stored there,
  * and that the rank table the reduction uses to find a sorted tuple's

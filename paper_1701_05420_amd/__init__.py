@@ -32,7 +32,8 @@ EXPORTS = [
     "cum_layout_query", "cum_workspace_size", "cum_center", "cum_moment_blocks", "cum_cumulants", "cum_unfold",
     "cum_stored_offset", "cum_batch_create", "cum_batch_run", "cum_batch_timestamps", "cum_batch_destroy",
     "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning", "cum_get_tuning",
-    "cum_batch_autotune", "cum_status_str", "cum_last_error",
+    "cum_batch_autotune", "cum_stream_create", "cum_stream_update", "cum_stream_cumulants", "cum_stream_count",
+    "cum_stream_reset", "cum_stream_destroy", "cum_status_str", "cum_last_error",
 ]
 SHAPES = {"32x32": 0, "32x64": 2}
 
@@ -68,6 +69,12 @@ _lib.cum_autotune.argtypes = [_VP, _I64, _I, _I64, _I, _I, _I, _VP, ctypes.POINT
 _lib.cum_set_tuning.argtypes = [_I64, _I, _I, _I, _I, ctypes.POINTER(Tuning)]
 _lib.cum_get_tuning.argtypes = [_I64, _I, _I, _I, _I, ctypes.POINTER(Tuning)]
 _lib.cum_batch_autotune.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(Tuning)]
+_lib.cum_stream_create.argtypes = [_I, _I, _I, _I, _VP, ctypes.POINTER(_VP)]
+_lib.cum_stream_update.argtypes = [_VP, _VP, _I64, _I64, _I, _VP]
+_lib.cum_stream_cumulants.argtypes = [_VP, _VP, ctypes.POINTER(_VP), _VP]
+_lib.cum_stream_count.argtypes = [_VP, ctypes.POINTER(_I64)]
+_lib.cum_stream_reset.argtypes = [_VP, _VP]
+_lib.cum_stream_destroy.argtypes = [_VP]
 _lib.cum_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]
 _lib.cum_status_str.argtypes = [_I]
 _lib.cum_status_str.restype = ctypes.c_char_p
@@ -302,6 +309,73 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             _lib.cum_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stream:
+    """A sliding window of samples: add and remove batches, read the window's
+    cumulants at any time (sums about a fixed shift, FP64)."""
+
+    def __init__(self, n: int, d_max: int, b: int, prec="f32", shift=None):
+        self.n, self.d_max, self.b, self.prec = n, d_max, b, _prec(prec)
+        sh = None
+        if shift is not None:
+            import numpy as np
+
+            arr = np.ascontiguousarray(np.asarray(shift, dtype=np.float64))
+            if arr.shape != (n,):
+                raise ValueError(f"shift must hold {n} values")
+            self._shift = arr
+            sh = arr.ctypes.data_as(_VP)
+        h = _VP()
+        _check(_lib.cum_stream_create(n, d_max, b, self.prec, sh, ctypes.byref(h)))
+        self._h = h
+
+    def _update(self, X, sign, stream):
+        torch = _torch()
+        _dev_check(X, torch.float64, "X")
+        if X.dim() != 2 or X.shape[1] != self.n or X.stride(1) != 1:
+            raise ValueError(f"X must be t x {self.n} with unit column stride")
+        _check(_lib.cum_stream_update(self._h, X.data_ptr(), X.shape[0], X.stride(0), sign, _stream(stream)))
+        self._keep = X
+
+    def add(self, X, stream=None):
+        """Add the samples X (t x n FP64 on the device) to the window."""
+        self._update(X, 1, stream)
+
+    def remove(self, X, stream=None):
+        """Remove samples X that were added before."""
+        self._update(X, -1, stream)
+
+    def count(self) -> int:
+        t = _I64()
+        _check(_lib.cum_stream_count(self._h, ctypes.byref(t)))
+        return int(t.value)
+
+    def cumulants(self, out=None, mean=None, stream=None):
+        """(mean, {d: c_d}) of the window, c_d in block storage."""
+        torch = _torch()
+        if out is None:
+            out = {d: torch.empty(layout(self.n, d, self.b)["elems"], dtype=torch.float64, device="cuda")
+                   for d in range(2, self.d_max + 1)}
+        if mean is None:
+            mean = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        ks = (_VP * (self.d_max - 1))(*[out[d].data_ptr() for d in range(2, self.d_max + 1)])
+        _check(_lib.cum_stream_cumulants(self._h, mean.data_ptr(), ks, _stream(stream)))
+        return mean, out
+
+    def reset(self, stream=None):
+        _check(_lib.cum_stream_reset(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cum_stream_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -696,10 +696,9 @@ static int red_lds_layout(const RedOrder *ro, int nords, bool recursion, RedArgs
     return ra.parts_off + (ra.parts_lds ? (int)(parts * 4) : 0);
 }
 
-// moment contraction + reduction for orders dlo..dhi into kappa (and the
-// recursion for d >= 4 when recursion is set)
-static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, double *const *outs, bool recursion,
-                             hipStream_t s) {
+// The contraction of orders dlo..dhi over the staged data Xc into the
+// per-chunk partial sums, then their sum over chunks into chunk 0.
+static cum_status run_contraction(CallPlan *c, const void *Xc, double *partial, hipStream_t s) {
     cum_status st = upload_call(*c);
     if (st) return st;
     MomentArgs ma;
@@ -718,7 +717,6 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
     ma.pad = 0;
     if (c->nitems > 0)
         HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, c->dhi, ma, (int)c->nitems, s); }));
-    // the sum over sample chunks, once for all orders
     SetRed sr0;
     memset(&sr0, 0, sizeof sr0);
     sr0.partial = partial;
@@ -727,8 +725,18 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
     sr0.t = c->t;
     if (c->nchunks > 1)
         HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_chunksum(nullptr, sr0, 1, c->stride, s); }));
-    // finalisation (+ recursion) in pairs of orders {d, d+1}: order d needs
-    // cumulants up to d-2 only, so a pair depends only on earlier pairs
+    return CUM_OK;
+}
+
+// Finalisation of orders dlo..dhi from summed moment sums S (one chunk, in
+// the call's partial-sum layout): M = S / t and, with recursion, the
+// cumulants, into outs (block storage of block size b).
+static cum_status run_finalize(CallPlan *c, double *sums, int64_t t, double *const *outs, bool recursion,
+                               hipStream_t s) {
+    cum_status st = upload_call(*c);
+    if (st) return st;
+    // in pairs of orders {d, d+1}: order d needs cumulants up to d-2 only, so
+    // a pair depends only on earlier pairs
     const RedOrder *red_d = (const RedOrder *)c->red_d.p;
     for (int d = c->dlo; d <= c->dhi; d += 2) {
         RedArgs ra;
@@ -742,10 +750,10 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
         ra.nb0 = c->red[i0].nblocks;
         ra.nbtot = ra.nb0 + (ra.nords == 2 ? c->red[i0 + 1].nblocks : 0);
         ra.sets = nullptr;
-        ra.set0.partial = partial;
+        ra.set0.partial = sums;
         ra.set0.stride = c->stride;
-        ra.set0.nchunks = c->nchunks;
-        ra.set0.t = c->t;
+        ra.set0.nchunks = 1;
+        ra.set0.t = t;
         for (int k = 0; k < MAXD - 1; ++k) ra.set0.kappa[k] = nullptr;
         for (int dd = c->dlo; dd <= c->dhi; ++dd) ra.set0.kappa[dd - 2] = outs[dd - c->dlo];
         ra.set0.stamp = nullptr;
@@ -768,6 +776,15 @@ static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, doubl
         }
     }
     return CUM_OK;
+}
+
+// moment contraction + reduction for orders dlo..dhi into outs (and the
+// recursion for d >= 4 when recursion is set)
+static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, double *const *outs, bool recursion,
+                             hipStream_t s) {
+    cum_status st;
+    if ((st = run_contraction(c, Xc, partial, s))) return st;
+    return run_finalize(c, partial, c->t, outs, recursion, s);
 }
 
 }  // namespace cum
@@ -1624,6 +1641,169 @@ cum_status cum_batch_autotune(cum_batch *p, const double *const *X_i, cum_tuning
 
 cum_status cum_batch_destroy(cum_batch *plan) {
     batch_free(plan);
+    return CUM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Streaming windows: FP64 moment sums about a fixed shift, updated by adding
+// and removing batches of samples, finalised on demand.
+// ---------------------------------------------------------------------------
+struct cum_stream {
+    int n = 0, d_max = 0, b = 0, prec = 0;
+    int64_t t = 0;          // samples in the window
+    bool have_shift = false;
+    int64_t stride = 0;     // sums of orders 2..d_max, each sorted variable tuple once
+    std::vector<int64_t> off;  // offset of order d in the sums (index d - 2)
+    CallPlan *last = nullptr;  // a plan of the window's shape (its finalisation records)
+    DevBuf shift_d, s1_d, delta_d, bmean_d, sums_d, central_d, ws_d;
+    size_t ws_bytes = 0;
+};
+
+cum_status cum_stream_create(int n, int d_max, int b, cum_prec prec, const double *shift, cum_stream **out) {
+    cum_status st;
+    if (!out) return fail(CUM_EINVAL, "NULL argument");
+    *out = nullptr;
+    if ((st = check_common(1, n, b)) || (st = check_prec(prec))) return st;
+    if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
+    for (int d = 2; d <= d_max; ++d)
+        if (ipow64(b, d) > INT32_MAX)
+            return fail(CUM_EUNSUPPORTED, "blocks of b^d = %d^%d entries (2^31 or more) are not supported", b, d);
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::unique_ptr<cum_stream> p(new cum_stream);
+    p->n = n;
+    p->d_max = d_max;
+    p->b = b;
+    p->prec = prec;
+    for (int d = 2; d <= d_max; ++d) {
+        OrderPlan *o;
+        if ((st = get_order(n, 1, d, &o))) return st;
+        p->off.push_back(p->stride);
+        p->stride += o->elems;
+    }
+    const size_t sb = (size_t)std::max<int64_t>(p->stride, 1) * sizeof(double), nb = (size_t)n * sizeof(double);
+    HIP_TRY(hipMalloc(&p->sums_d.p, sb));
+    HIP_TRY(hipMalloc(&p->central_d.p, sb));
+    HIP_TRY(hipMalloc(&p->shift_d.p, nb));
+    HIP_TRY(hipMalloc(&p->s1_d.p, nb));
+    HIP_TRY(hipMalloc(&p->delta_d.p, nb));
+    HIP_TRY(hipMalloc(&p->bmean_d.p, nb));
+    HIP_TRY(hipMemset(p->sums_d.p, 0, sb));
+    HIP_TRY(hipMemset(p->s1_d.p, 0, nb));
+    if (shift) {
+        HIP_TRY(hipMemcpy(p->shift_d.p, shift, nb, hipMemcpyHostToDevice));
+        p->have_shift = true;
+    }
+    *out = p.release();
+    return CUM_OK;
+}
+
+cum_status cum_stream_update(cum_stream *p, const double *X, int64_t t, int64_t ldx, int sign, void *stream) {
+    cum_status st;
+    if (!p || !X) return fail(CUM_EINVAL, "NULL argument");
+    if (t < 1) return fail(CUM_EINVAL, "t must be >= 1 (got %lld)", (long long)t);
+    if (ldx < p->n) return fail(CUM_EINVAL, "ldx (%lld) < n (%d)", (long long)ldx, p->n);
+    if (sign != 1 && sign != -1) return fail(CUM_EINVAL, "sign must be +1 (add) or -1 (remove)");
+    if (sign < 0 && p->t - t < 0)
+        return fail(CUM_EINVAL, "removing %lld samples from a window of %lld", (long long)t, (long long)p->t);
+    if (sign < 0 && !p->have_shift) return fail(CUM_EINVAL, "nothing has been added yet");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    const int n = p->n;
+    // the contraction fills the layout of block size 1 (each sorted tuple once)
+    CallPlan *c;
+    if ((st = get_call_cfg(n, p->b, 1, 2, p->d_max, p->prec, default_shape(p->prec), DEFAULT_TARGET, t, &c)))
+        return st;
+    if ((st = upload_call(*c))) return st;
+    int groups;
+    int64_t rows_per;
+    center_groups(t, groups, rows_per);
+    const size_t xbytes = staged_bytes(t, n, p->prec), cbytes = align_up((size_t)groups * n * 2 * 8);
+    const size_t need = xbytes + cbytes + align_up((size_t)c->nchunks * c->stride * 8);
+    if (need > p->ws_bytes) {
+        // the old workspace may still be read by work queued on the stream
+        HIP_TRY(hipStreamSynchronize(s));
+        if (p->ws_d.p) {
+            (void)hipFree(p->ws_d.p);
+            p->ws_d.p = nullptr;
+            p->ws_bytes = 0;
+        }
+        HIP_TRY(hipMalloc(&p->ws_d.p, need));
+        p->ws_bytes = need;
+    }
+    char *Xst = (char *)p->ws_d.p, *cw = Xst + xbytes;
+    double *partial = (double *)(cw + cbytes);
+    double *shift = (double *)p->shift_d.p, *bmean = (double *)p->bmean_d.p;
+    // the batch's mean; the first batch's mean becomes the shift if none was given
+    if ((st = center_impl(X, t, n, ldx, p->prec, bmean, nullptr, cw, cbytes, s))) return st;
+    if (!p->have_shift) {
+        HIP_TRY(hipMemcpyAsync(shift, bmean, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        p->have_shift = true;
+    }
+    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] {
+        return launch_stream_sum1((double *)p->s1_d.p, bmean, shift, (double)sign * (double)t, n, s);
+    }));
+    // the batch's sums of products of x - c, added into (or taken from) the window's
+    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, shift, Xst, p->prec, true, true, s); }));
+    if ((st = run_contraction(c, Xst, partial, s))) return st;
+    HIP_TRY(timed(CUM_KIND_REDUCE, s,
+                  [&] { return launch_axpy((double *)p->sums_d.p, partial, (double)sign, p->stride, s); }));
+    p->t += sign * t;
+    p->last = c;
+    return CUM_OK;
+}
+
+cum_status cum_stream_cumulants(cum_stream *p, double *mean, double *const *kappa, void *stream) {
+    cum_status st;
+    if (!p || !kappa) return fail(CUM_EINVAL, "NULL argument");
+    for (int d = 2; d <= p->d_max; ++d)
+        if (!kappa[d - 2]) return fail(CUM_EINVAL, "kappa[%d] is NULL", d - 2);
+    if (p->t < 1 || !p->last) return fail(CUM_EINVAL, "the window holds no samples");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    const double tt = (double)p->t;
+    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] {
+        return launch_stream_mean((const double *)p->s1_d.p, (const double *)p->shift_d.p, tt, p->n,
+                                  (double *)p->delta_d.p, mean, s);
+    }));
+    RecArgs ra;
+    memset(&ra, 0, sizeof ra);
+    ra.sums = (const double *)p->sums_d.p;
+    ra.central = (double *)p->central_d.p;
+    ra.delta = (const double *)p->delta_d.p;
+    for (int d = 2; d <= p->d_max; ++d) ra.off[d] = p->off[d - 2];
+    ra.t = tt;
+    ra.n = p->n;
+    for (int d = 2; d <= p->d_max; ++d) {
+        OrderPlan *o;
+        if ((st = get_order(p->n, 1, d, &o)) || (st = upload_order(*o))) return st;
+        ra.tuples = (const uint8_t *)o->tuples_d.p;
+        ra.count = o->nblocks;
+        ra.d = d;
+        HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_recentre(ra, s); }));
+    }
+    // the central moments are already divided by t
+    return run_finalize(p->last, (double *)p->central_d.p, 1, kappa, true, s);
+}
+
+cum_status cum_stream_count(cum_stream *p, int64_t *t) {
+    if (!p || !t) return fail(CUM_EINVAL, "NULL argument");
+    *t = p->t;
+    return CUM_OK;
+}
+
+cum_status cum_stream_reset(cum_stream *p, void *stream) {
+    if (!p) return fail(CUM_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemsetAsync(p->sums_d.p, 0, (size_t)std::max<int64_t>(p->stride, 1) * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(p->s1_d.p, 0, (size_t)p->n * sizeof(double), s));
+    p->t = 0;
+    return CUM_OK;
+}
+
+cum_status cum_stream_destroy(cum_stream *p) {
+    if (p && p->ws_d.p) (void)hipDeviceSynchronize();
+    delete p;
     return CUM_OK;
 }
 

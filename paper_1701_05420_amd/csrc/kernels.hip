@@ -999,6 +999,123 @@ hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
+// Streaming sums.  Sums over samples are additive over disjoint sample ranges
+// (the chunk decomposition of Alg. 3, eq. mapred), so a window's moment sums
+// are the sum of its batches' sums, and a batch leaves the window by
+// subtracting its sums again.  Sums are kept about a fixed shift c; the
+// central moments follow by expanding prod_k (y_k - delta_k), y = x - c,
+// delta = mean(y), over the subsets of positions.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void axpy_kernel(double *y, const double *x, double a, int64_t count) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256)
+        y[e] += a * x[e];
+}
+
+hipError_t launch_axpy(double *y, const double *x, double a, int64_t count, hipStream_t s) {
+    int64_t g = (count + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)g), dim3(256), 0, s, y, x, a, count);
+    return hipGetLastError();
+}
+
+// s1 += tb * (batch mean - c): the batch's sum of shifted samples (tb = +-t_B)
+__global__ void stream_sum1_kernel(double *s1, const double *bmean, const double *shift, double tb, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) s1[i] += tb * (bmean[i] - shift[i]);
+}
+
+hipError_t launch_stream_sum1(double *s1, const double *bmean, const double *shift, double tb, int n, hipStream_t s) {
+    hipLaunchKernelGGL(stream_sum1_kernel, dim3((n + 255) / 256), dim3(256), 0, s, s1, bmean, shift, tb, n);
+    return hipGetLastError();
+}
+
+// delta = s1 / t (mean of the shifted data), mean = c + delta
+__global__ void stream_mean_kernel(const double *s1, const double *shift, double t, int n, double *delta,
+                                   double *mean) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        const double dl = s1[i] / t;
+        delta[i] = dl;
+        if (mean) mean[i] = shift[i] + dl;
+    }
+}
+
+hipError_t launch_stream_mean(const double *s1, const double *shift, double t, int n, double *delta, double *mean,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(stream_mean_kernel, dim3((n + 255) / 256), dim3(256), 0, s, s1, shift, t, n, delta, mean);
+    return hipGetLastError();
+}
+
+// Central moment of the sorted variable tuple u (order D): the sum over
+// position subsets A of prod_{k not in A} (-delta_{u_k}) times the moment of
+// the shifted data at u_A (1 for A empty, delta for one position, the summed
+// products / t otherwise, read at the rank of the sorted sub-tuple).  The
+// subsets run in increasing mask order.
+template <int D>
+__global__ __launch_bounds__(256) void recentre_kernel(RecArgs a) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.count; e += (int64_t)gridDim.x * 256) {
+        int u[D];
+        double dl[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            u[k] = a.tuples[e * D + k];
+            dl[k] = a.delta[u[k]];
+        }
+        double acc = 0.0;
+        for (unsigned mask = 0; mask < (1u << D); ++mask) {
+            const int m = __popc(mask);
+            double coef = 1.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (!(mask >> k & 1u)) coef *= -dl[k];
+            double v;
+            if (m == 0) {
+                v = 1.0;
+            } else if (m == 1) {
+                v = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    if (mask >> k & 1u) v = dl[k];
+            } else {
+                int64_t rank = 0;
+                int prev = 0, k2 = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    if (mask >> k & 1u) {
+                        rank += c_binom.c[a.n - prev + m - k2 - 1][m - k2] - c_binom.c[a.n - u[k] + m - k2 - 1][m - k2];
+                        prev = u[k];
+                        ++k2;
+                    }
+                v = a.sums[a.off[m] + rank] / a.t;
+            }
+            acc += coef * v;
+        }
+        a.central[a.off[D] + e] = acc;
+    }
+}
+
+hipError_t launch_recentre(const RecArgs &a, hipStream_t s) {
+    int64_t g = (a.count + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    const dim3 grid((unsigned)g), block(256);
+    switch (a.d) {
+        case 2: hipLaunchKernelGGL(recentre_kernel<2>, grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(recentre_kernel<3>, grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL(recentre_kernel<4>, grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL(recentre_kernel<5>, grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL(recentre_kernel<6>, grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL(recentre_kernel<7>, grid, block, 0, s, a); break;
+        case 8: hipLaunchKernelGGL(recentre_kernel<8>, grid, block, 0, s, a); break;
+        case 9: hipLaunchKernelGGL(recentre_kernel<9>, grid, block, 0, s, a); break;
+        case 10: hipLaunchKernelGGL(recentre_kernel<10>, grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Unfold to dense: entry i is read at the stored position of sorted(i).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void unfold_kernel(const double *blocks, int n, int d, int b, int nbar,

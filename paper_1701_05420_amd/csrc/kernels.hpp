@@ -36,6 +36,19 @@ struct RedArgs {
     SetRed set0;
 };
 
+// Re-centring of one order: raw moment sums of shifted data (each sorted
+// variable tuple once) to central moments.
+struct RecArgs {
+    const double *sums;      // sums of products of shifted data, order m at off[m]
+    double *central;         // central moments (already divided by t), same layout
+    const double *delta;     // n: mean of the shifted data
+    const uint8_t *tuples;   // count x d sorted variable tuples of order d
+    int64_t off[MAXD + 1];   // layout offset of order m (m = 2..d)
+    int64_t count;           // tuples of order d
+    double t;                // samples (moments are sums / t)
+    int32_t n, d;
+};
+
 // Wave task shapes: one 32-row block by WN 32-column blocks.
 enum TileShape { TS_1x1 = 0, TS_1x2 = 2 };
 
@@ -46,6 +59,11 @@ hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const doub
 hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s);
 hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, hipStream_t s);
 hipError_t launch_chunksum(const SetRed *sets, const SetRed &set0, int nsets, int64_t entries, hipStream_t s);
+hipError_t launch_axpy(double *y, const double *x, double a, int64_t count, hipStream_t s);
+hipError_t launch_stream_sum1(double *s1, const double *bmean, const double *shift, double tb, int n, hipStream_t s);
+hipError_t launch_stream_mean(const double *s1, const double *shift, double t, int n, double *delta, double *mean,
+                              hipStream_t s);
+hipError_t launch_recentre(const RecArgs &a, hipStream_t s);
 hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,
                          hipStream_t s);
 hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s);

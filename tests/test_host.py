@@ -124,6 +124,16 @@ def test_entry_points_validate_before_touching_the_device(pc):
     assert _raw(pc, "cum_moment_blocks", P, 0, 10, 4, 4, 2, P, P, 8, N) == -2
     assert _raw(pc, "cum_center", P, 10, 4, 2, 0, P, P, P, 1 << 20, N) == -1                # ldx < n
     assert _raw(pc, "cum_unfold", P, 4, 11, 2, P, N) == -1
+    # streams: arguments are checked before any device memory is allocated
+    h = ctypes.c_void_p()
+    assert _raw(pc, "cum_stream_create", 0, 4, 1, 0, N, ctypes.byref(h)) == -1              # n = 0
+    assert _raw(pc, "cum_stream_create", 5, 11, 2, 0, N, ctypes.byref(h)) == -1             # d_max > 10
+    assert _raw(pc, "cum_stream_create", 5, 4, 6, 0, N, ctypes.byref(h)) == -1              # b > n
+    assert _raw(pc, "cum_stream_create", 5, 4, 2, 9, N, ctypes.byref(h)) == -4              # prec
+    assert _raw(pc, "cum_stream_create", 5, 4, 2, 0, N, N) == -1
+    assert _raw(pc, "cum_stream_update", N, P, 10, 5, 1, N) == -1
+    assert _raw(pc, "cum_stream_cumulants", N, P, kap, N) == -1
+    assert _raw(pc, "cum_stream_count", N, ctypes.byref(ctypes.c_int64())) == -1
 
 
 def test_tuning_round_trip_and_validation(pc):
