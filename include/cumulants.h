@@ -267,6 +267,16 @@ cum_status cum_stream_update(cum_stream *s, const double *X, int64_t t, int64_t 
  * window holds no samples.  Asynchronous on stream. */
 cum_status cum_stream_cumulants(cum_stream *s, double *mean, double *const *kappa, void *stream);
 
+/* The same outputs by the general formula (eq. cumfmom, Section 5.3): each
+ * cumulant as the sum over all B(d) set partitions of its positions of
+ * (k-1)! (-1)^(k-1) (k parts) times the product of the window's moments
+ * about the shift at the parts, with no centring and no recursion.  With
+ * shift 0 the moments are raw moments: the general algorithm the paper
+ * compares against, which loses accuracy to cancellation as the mean grows
+ * against the spread.  Cost per entry grows with B(d) (15 at d = 4, 203 at
+ * 6, 115975 at 10).  Asynchronous on stream. */
+cum_status cum_stream_cumulants_moebius(cum_stream *s, double *mean, double *const *kappa, void *stream);
+
 /* Host only.  Samples in the window. */
 cum_status cum_stream_count(cum_stream *s, int64_t *t /* host out */);
 

@@ -32,7 +32,8 @@ EXPORTS = [
     "cum_layout_query", "cum_workspace_size", "cum_center", "cum_moment_blocks", "cum_cumulants", "cum_unfold",
     "cum_stored_offset", "cum_batch_create", "cum_batch_run", "cum_batch_timestamps", "cum_batch_destroy",
     "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning", "cum_get_tuning",
-    "cum_batch_autotune", "cum_stream_create", "cum_stream_update", "cum_stream_cumulants", "cum_stream_count",
+    "cum_batch_autotune", "cum_stream_create", "cum_stream_update", "cum_stream_cumulants", "cum_stream_cumulants_moebius",
+    "cum_stream_count",
     "cum_stream_reset", "cum_stream_destroy", "cum_status_str", "cum_last_error",
 ]
 SHAPES = {"32x32": 0, "32x64": 2}
@@ -72,6 +73,7 @@ _lib.cum_batch_autotune.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(Tun
 _lib.cum_stream_create.argtypes = [_I, _I, _I, _I, _VP, ctypes.POINTER(_VP)]
 _lib.cum_stream_update.argtypes = [_VP, _VP, _I64, _I64, _I, _VP]
 _lib.cum_stream_cumulants.argtypes = [_VP, _VP, ctypes.POINTER(_VP), _VP]
+_lib.cum_stream_cumulants_moebius.argtypes = [_VP, _VP, ctypes.POINTER(_VP), _VP]
 _lib.cum_stream_count.argtypes = [_VP, ctypes.POINTER(_I64)]
 _lib.cum_stream_reset.argtypes = [_VP, _VP]
 _lib.cum_stream_destroy.argtypes = [_VP]
@@ -358,16 +360,21 @@ class Stream:
         _check(_lib.cum_stream_count(self._h, ctypes.byref(t)))
         return int(t.value)
 
-    def cumulants(self, out=None, mean=None, stream=None):
-        """(mean, {d: c_d}) of the window, c_d in block storage."""
+    def cumulants(self, out=None, mean=None, stream=None, method="recursion"):
+        """(mean, {d: c_d}) of the window, c_d in block storage; method
+        "recursion" (centred moments, partition recursion) or "moebius" (the
+        general formula on the moments about the shift)."""
         torch = _torch()
+        if method not in ("recursion", "moebius"):
+            raise ValueError("method is 'recursion' or 'moebius'")
         if out is None:
             out = {d: torch.empty(layout(self.n, d, self.b)["elems"], dtype=torch.float64, device="cuda")
                    for d in range(2, self.d_max + 1)}
         if mean is None:
             mean = torch.empty(self.n, dtype=torch.float64, device="cuda")
         ks = (_VP * (self.d_max - 1))(*[out[d].data_ptr() for d in range(2, self.d_max + 1)])
-        _check(_lib.cum_stream_cumulants(self._h, mean.data_ptr(), ks, _stream(stream)))
+        fn = _lib.cum_stream_cumulants if method == "recursion" else _lib.cum_stream_cumulants_moebius
+        _check(fn(self._h, mean.data_ptr(), ks, _stream(stream)))
         return mean, out
 
     def reset(self, stream=None):

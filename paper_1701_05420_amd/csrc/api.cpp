@@ -155,6 +155,34 @@ static std::vector<std::vector<uint16_t>> recursion_partitions(int d) {
     return out;
 }
 
+// Every set partition of d positions (restricted growth strings, in their
+// lexicographic order), each as its part masks in order of first position,
+// with the weight (k-1)! (-1)^(k-1) of a partition into k parts (the
+// moment-to-cumulant formula eq. cumfmom).
+static void all_partitions(int d, std::vector<std::vector<uint16_t>> &parts, std::vector<double> &weight) {
+    std::vector<int> a(d, 0);
+    while (true) {
+        int k = 0;
+        for (int q = 0; q < d; ++q) k = std::max(k, a[q] + 1);
+        std::vector<uint16_t> masks(k, 0);
+        for (int q = 0; q < d; ++q) masks[a[q]] |= (uint16_t)(1u << q);
+        double f = 1.0;
+        for (int q = 2; q < k; ++q) f *= q;
+        parts.push_back(masks);
+        weight.push_back((k - 1) % 2 ? -f : f);
+        int q = d - 1;
+        while (q >= 1) {
+            int lim = 0;
+            for (int r = 0; r < q; ++r) lim = std::max(lim, a[r] + 1);
+            if (a[q] < lim) break;
+            --q;
+        }
+        if (q < 1) break;
+        ++a[q];
+        for (int r = q + 1; r < d; ++r) a[r] = 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // device buffers owned by the library
 // ---------------------------------------------------------------------------
@@ -974,6 +1002,36 @@ cum_status cum_plan_check(int n, int d, int b) {
         }
         if (r != (int64_t)i * be) return fail(CUM_EINVAL, "d=%d: rank table gives %lld for tuple %zu", d, (long long)r, i);
     }
+    // the general formula's table: every set partition once, as many as the
+    // Bell number B(d) (Bell triangle), with weights (k-1)! (-1)^(k-1)
+    {
+        std::vector<std::vector<uint16_t>> ap;
+        std::vector<double> w;
+        all_partitions(d, ap, w);
+        std::vector<int64_t> row{1};
+        for (int m = 1; m < d; ++m) {
+            std::vector<int64_t> nx{row.back()};
+            for (int64_t v : row) nx.push_back(nx.back() + v);
+            row = nx;
+        }
+        if ((int64_t)ap.size() != row.back())
+            return fail(CUM_EINVAL, "d=%d: %zu set partitions, expected %lld", d, ap.size(), (long long)row.back());
+        std::set<std::vector<uint16_t>> seen;
+        for (size_t z = 0; z < ap.size(); ++z) {
+            unsigned cover = 0;
+            for (uint16_t m : ap[z]) {
+                if (!m || (cover & m)) return fail(CUM_EINVAL, "d=%d: set partition %zu overlaps", d, z);
+                cover |= m;
+            }
+            double f = 1.0;
+            for (size_t q = 2; q < ap[z].size(); ++q) f *= (double)q;
+            if (cover != (1u << d) - 1u || w[z] != ((ap[z].size() - 1) % 2 ? -f : f))
+                return fail(CUM_EINVAL, "d=%d: set partition %zu", d, z);
+            auto sorted = ap[z];
+            std::sort(sorted.begin(), sorted.end());
+            if (!seen.insert(sorted).second) return fail(CUM_EINVAL, "d=%d: set partition %zu repeated", d, z);
+        }
+    }
     // recursion tables: every partition splits the d positions into >= 2
     // disjoint parts of >= 2 positions, no partition twice, and as many as
     // there are (a(d) - 1, a(n) = sum_k C(n-1, k) a(n-1-k) counting the set
@@ -1783,6 +1841,71 @@ cum_status cum_stream_cumulants(cum_stream *p, double *mean, double *const *kapp
     }
     // the central moments are already divided by t
     return run_finalize(p->last, (double *)p->central_d.p, 1, kappa, true, s);
+}
+
+// device tables of all_partitions, per order
+struct MoebTable {
+    int npart = 0;
+    DevBuf parts_d, weight_d;
+};
+static std::map<int, std::unique_ptr<MoebTable>> g_moeb;
+
+static cum_status get_moebius(int d, MoebTable **out) {
+    auto it = g_moeb.find(d);
+    if (it != g_moeb.end()) {
+        *out = it->second.get();
+        return CUM_OK;
+    }
+    std::vector<std::vector<uint16_t>> ap;
+    std::vector<double> w;
+    all_partitions(d, ap, w);
+    std::vector<uint16_t> flat;
+    for (const auto &pm : ap)
+        for (int k = 0; k < d; ++k) flat.push_back(k < (int)pm.size() ? pm[k] : 0);
+    std::unique_ptr<MoebTable> t(new MoebTable);
+    t->npart = (int)ap.size();
+    cum_status st;
+    if ((st = upload(t->parts_d, flat)) || (st = upload(t->weight_d, w))) return st;
+    *out = t.get();
+    g_moeb[d] = std::move(t);
+    return CUM_OK;
+}
+
+cum_status cum_stream_cumulants_moebius(cum_stream *p, double *mean, double *const *kappa, void *stream) {
+    cum_status st;
+    if (!p || !kappa) return fail(CUM_EINVAL, "NULL argument");
+    for (int d = 2; d <= p->d_max; ++d)
+        if (!kappa[d - 2]) return fail(CUM_EINVAL, "kappa[%d] is NULL", d - 2);
+    if (p->t < 1 || !p->last) return fail(CUM_EINVAL, "the window holds no samples");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    const double tt = (double)p->t;
+    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] {
+        return launch_stream_mean((const double *)p->s1_d.p, (const double *)p->shift_d.p, tt, p->n,
+                                  (double *)p->delta_d.p, mean, s);
+    }));
+    MoebArgs ma;
+    memset(&ma, 0, sizeof ma);
+    ma.sums = (const double *)p->sums_d.p;
+    ma.out = (double *)p->central_d.p;
+    ma.delta = (const double *)p->delta_d.p;
+    for (int d = 2; d <= p->d_max; ++d) ma.off[d] = p->off[d - 2];
+    ma.t = tt;
+    ma.n = p->n;
+    for (int d = 2; d <= p->d_max; ++d) {
+        OrderPlan *o;
+        MoebTable *mt;
+        if ((st = get_order(p->n, 1, d, &o)) || (st = upload_order(*o)) || (st = get_moebius(d, &mt))) return st;
+        ma.tuples = (const uint8_t *)o->tuples_d.p;
+        ma.count = o->nblocks;
+        ma.parts = (const uint16_t *)mt->parts_d.p;
+        ma.weight = (const double *)mt->weight_d.p;
+        ma.npart = mt->npart;
+        ma.d = d;
+        HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_moebius(ma, s); }));
+    }
+    // expand each tuple's cumulant to every stored copy (t = 1: no division)
+    return run_finalize(p->last, (double *)p->central_d.p, 1, kappa, false, s);
 }
 
 cum_status cum_stream_count(cum_stream *p, int64_t *t) {

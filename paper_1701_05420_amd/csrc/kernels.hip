@@ -1115,6 +1115,72 @@ hipError_t launch_recentre(const RecArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Cumulant of the sorted variable tuple u (order D) from the moments of the
+// shifted data (eq. cumfmom, the general formula of Section 5.3): the sum
+// over every set partition of the D positions, in table order, of its weight
+// (k-1)! (-1)^(k-1) (k parts) times the product over its parts B of the
+// moment at u_B (delta for one position, the summed products / t otherwise).
+// Cumulants of order >= 2 do not depend on the shift.
+template <int D>
+__global__ __launch_bounds__(256) void moebius_kernel(MoebArgs a) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.count; e += (int64_t)gridDim.x * 256) {
+        int u[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) u[k] = a.tuples[e * D + k];
+        double acc = 0.0;
+        for (int z = 0; z < a.npart; ++z) {
+            double prod = a.weight[z];
+            for (int pt = 0; pt < D; ++pt) {
+                const unsigned mask = __builtin_amdgcn_readfirstlane((int)a.parts[z * D + pt]);
+                if (!mask) break;
+                const int m = __popc(mask);
+                double v;
+                if (m == 1) {
+                    v = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        if (mask >> k & 1u) v = a.delta[u[k]];
+                } else {
+                    int64_t rank = 0;
+                    int prev = 0, k2 = 0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        if (mask >> k & 1u) {
+                            rank += c_binom.c[a.n - prev + m - k2 - 1][m - k2] -
+                                    c_binom.c[a.n - u[k] + m - k2 - 1][m - k2];
+                            prev = u[k];
+                            ++k2;
+                        }
+                    v = a.sums[a.off[m] + rank] / a.t;
+                }
+                prod *= v;
+            }
+            acc += prod;
+        }
+        a.out[a.off[D] + e] = acc;
+    }
+}
+
+hipError_t launch_moebius(const MoebArgs &a, hipStream_t s) {
+    int64_t g = (a.count + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    const dim3 grid((unsigned)g), block(256);
+    switch (a.d) {
+        case 2: hipLaunchKernelGGL(moebius_kernel<2>, grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(moebius_kernel<3>, grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL(moebius_kernel<4>, grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL(moebius_kernel<5>, grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL(moebius_kernel<6>, grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL(moebius_kernel<7>, grid, block, 0, s, a); break;
+        case 8: hipLaunchKernelGGL(moebius_kernel<8>, grid, block, 0, s, a); break;
+        case 9: hipLaunchKernelGGL(moebius_kernel<9>, grid, block, 0, s, a); break;
+        case 10: hipLaunchKernelGGL(moebius_kernel<10>, grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Unfold to dense: entry i is read at the stored position of sorted(i).
 // ---------------------------------------------------------------------------

@@ -49,6 +49,21 @@ struct RecArgs {
     int32_t n, d;
 };
 
+// Cumulants of one order directly from the moments of shifted data by the
+// Moebius-weighted sum over all set partitions of the positions.
+struct MoebArgs {
+    const double *sums;      // sums of products of shifted data, order m at off[m]
+    double *out;             // cumulants of order d, each sorted tuple once, at off[d]
+    const double *delta;     // n: mean of the shifted data (the order-1 moment)
+    const uint8_t *tuples;   // count x d sorted variable tuples of order d
+    const uint16_t *parts;   // npart x d position masks (0 = no more parts)
+    const double *weight;    // npart: (k-1)! (-1)^(k-1) for a partition of k parts
+    int64_t off[MAXD + 1];
+    int64_t count;
+    double t;
+    int32_t n, d, npart, pad;
+};
+
 // Wave task shapes: one 32-row block by WN 32-column blocks.
 enum TileShape { TS_1x1 = 0, TS_1x2 = 2 };
 
@@ -64,6 +79,7 @@ hipError_t launch_stream_sum1(double *s1, const double *bmean, const double *shi
 hipError_t launch_stream_mean(const double *s1, const double *shift, double t, int n, double *delta, double *mean,
                               hipStream_t s);
 hipError_t launch_recentre(const RecArgs &a, hipStream_t s);
+hipError_t launch_moebius(const MoebArgs &a, hipStream_t s);
 hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,
                          hipStream_t s);
 hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s);

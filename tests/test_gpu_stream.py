@@ -136,3 +136,51 @@ def test_stream_errors(dev):
     with pytest.raises(pc.CumulantError):
         st.cumulants()
     st.close()
+
+
+def check_moebius(orc, st, Xw, dmax, b, tol, exact=False):
+    import torch
+
+    mean, K = st.cumulants(method="moebius")
+    torch.cuda.synchronize()
+    om, OK = orc.cumulants_dense(Xw, dmax)
+    assert np.abs(mean.cpu().numpy() - om).max() <= 1e-13 * max(1.0, np.abs(Xw).max())
+    for d in range(2, dmax + 1):
+        want = orc.fold(OK[d], b)
+        got = K[d].cpu().numpy()
+        if exact:
+            assert np.array_equal(got, want), (d, np.abs(got - want).max())
+        else:
+            e = rel(got, want)
+            say(f"  general formula e_{d} = {e:.3e}")
+            assert e <= tol, (d, e)
+
+
+@pytest.mark.parametrize("n,b,dmax", [(9, 3, 6), (5, 2, 8)])
+def test_moebius_on_raw_moments(dev, orc, n, b, dmax):
+    """The general formula (eq. cumfmom) on raw moments (shift 0) of data whose
+    mean is small against its spread, against the oracle's recursion on
+    centred data."""
+    torch, pc = dev
+    Xs = [workloads.t_gamma_mix(t=t, n=n, seed=800 + t) + 0.25 for t in (1500, 2200)]
+    st = pc.Stream(n, dmax, b, "f64", shift=np.zeros(n))
+    for X in Xs:
+        st.add(torch.from_numpy(X).cuda())
+    say(f"general formula n={n} b={b} dmax={dmax}")
+    check_moebius(orc, st, np.concatenate(Xs), dmax, b, 1e-10)
+    st.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3"])
+def test_moebius_integer_exact(dev, orc, prec):
+    """Zero-mean small-integer data, t = 512, shift 0: every moment and every
+    product of the formula is a short dyadic number, so the general formula
+    and the recursion agree bit for bit."""
+    torch, pc = dev
+    n, b, dmax = 6, 4, 6
+    Xs = [workloads.dyadic_integers(t=t, n=n, seed=900 + t, lo=-2, hi=2) for t in (256, 128, 128)]
+    st = pc.Stream(n, dmax, b, prec, shift=np.zeros(n))
+    for X in Xs:
+        st.add(torch.from_numpy(X).cuda())
+    check_moebius(orc, st, np.concatenate(Xs), dmax, b, 0.0, exact=True)
+    st.close()
