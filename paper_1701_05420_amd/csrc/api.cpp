@@ -299,8 +299,13 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
     const int nr_real = (int)o.rows.size(), nc_real = (int)o.cols.size();
     o.nr = (nr_real + FEAT_BLOCK - 1) / FEAT_BLOCK * FEAT_BLOCK;
     o.nc = (nc_real + FEAT_BLOCK - 1) / FEAT_BLOCK * FEAT_BLOCK;
-    Feat padr{0, INT32_MAX, {(uint8_t)n, (uint8_t)n, (uint8_t)n, (uint8_t)n}};
-    Feat padc{0, -1, {(uint8_t)n, (uint8_t)n, (uint8_t)n, (uint8_t)n}};
+    // padding rows and columns multiply the zero row only
+    Feat padr, padc;
+    memset(&padr, 0, sizeof padr);
+    padr.blk = INT32_MAX;
+    for (int k = 0; k < MAXH; ++k) padr.var[k] = (uint8_t)n;
+    padc = padr;
+    padc.blk = -1;
     o.rows.resize(o.nr, padr);
     o.cols.resize(o.nc, padc);
     for (int rb = 0; rb < o.nr / FEAT_BLOCK; ++rb) {
@@ -500,9 +505,20 @@ static RedOrder red_order(const OrderPlan &o, const OrderPlan &po, int64_t poff)
 // call plan: all orders dlo..dhi of one (n, b), one precision and tile shape,
 // one sample count.
 // ---------------------------------------------------------------------------
+// The work items of one sample-chunk count: (tile, chunk) pairs in launch order.
+struct ItemSet {
+    std::vector<Item> items;
+    bool uploaded = false;
+    DevBuf items_d;
+};
+
+// Everything about a call that does not depend on its sample count: the
+// orders' tables, the tiles, the finalisation records, and the work items of
+// each chunk count met so far (at most one per chunk count, which the target
+// item count bounds).
 struct CallPlan {
-    int n = 0, b = 0, bi = 0, dlo = 0, dhi = 0, prec = 0, shape = 0;
-    int64_t t = 0, nstages = 0, chunk_stages = 0, nchunks = 0, nitems = 0;
+    int n = 0, b = 0, bi = 0, dlo = 0, dhi = 0, prec = 0, shape = 0, target = 0;
+    int64_t ntiles = 0;
     int64_t stride = 0;               // partial sums of all orders, block size bi
     int64_t kstride = 0;              // outputs of all orders, block size b
     std::vector<OrderPlan *> orders;  // output layout (block size b), index d - dlo
@@ -511,15 +527,22 @@ struct CallPlan {
     std::vector<int64_t> pout_off;    // partial-sum offsets, index d - dlo
     std::vector<OrderDev> ods;
     std::vector<TileDev> tdev;
-    std::vector<Item> items;
     std::vector<RedOrder> red;        // index d - dlo
+    std::map<int64_t, std::unique_ptr<ItemSet>> itemsets;  // by chunk count
     bool uploaded = false;
-    DevBuf ords_d, tiles_d, items_d, red_d;
+    DevBuf ords_d, tiles_d, red_d;
+};
+
+// One call: its plan and the split of its t samples into chunks of whole stages.
+struct Call {
+    CallPlan *c = nullptr;
+    ItemSet *is = nullptr;
+    int64_t t = 0, nstages = 0, chunk_stages = 0, nchunks = 0;
 };
 
 // Upload the call's order tables (filling in their device pointers) and its
 // tile, item and reduction records.
-static cum_status upload_call(CallPlan &c) {
+static cum_status upload_plan(CallPlan &c) {
     if (c.uploaded) return CUM_OK;
     cum_status st;
     c.ods.clear();
@@ -529,14 +552,22 @@ static cum_status upload_call(CallPlan &c) {
         c.ods.push_back(order_dev(*c.corders[i], c.pout_off[i]));
         c.red.push_back(red_order(*c.orders[i], *c.corders[i], c.pout_off[i]));
     }
-    if ((st = upload(c.ords_d, c.ods)) || (st = upload(c.tiles_d, c.tdev)) || (st = upload(c.items_d, c.items)) ||
-        (st = upload(c.red_d, c.red)))
-        return st;
+    if ((st = upload(c.ords_d, c.ods)) || (st = upload(c.tiles_d, c.tdev)) || (st = upload(c.red_d, c.red))) return st;
     c.uploaded = true;
     return CUM_OK;
 }
 
-static std::map<std::tuple<int, int, int, int, int, int, int, int, int64_t>, std::unique_ptr<CallPlan>> g_calls;
+static cum_status upload_call(const Call &k) {
+    cum_status st;
+    if ((st = upload_plan(*k.c))) return st;
+    if (!k.is->uploaded) {
+        if ((st = upload(k.is->items_d, k.is->items))) return st;
+        k.is->uploaded = true;
+    }
+    return CUM_OK;
+}
+
+static std::map<std::tuple<int, int, int, int, int, int, int, int>, std::unique_ptr<CallPlan>> g_calls;
 
 // Tuned choices: (n, b, dlo, dhi, prec, t) -> (shape, target items, inner block size).
 struct Tuning {
@@ -592,61 +623,16 @@ constexpr int DEFAULT_TARGET = 4096;
 // block size 1) unless tuning chose otherwise.
 static int default_inner(int) { return 1; }
 
-static cum_status get_call_cfg(int n, int b, int bi, int dlo, int dhi, int prec, int shape, int target, int64_t t,
-                               CallPlan **out) {
-    auto key = std::make_tuple(n, b, bi, dlo, dhi, prec, shape, target, t);
-    auto it = g_calls.find(key);
-    if (it != g_calls.end()) {
-        *out = it->second.get();
-        return CUM_OK;
-    }
-    std::unique_ptr<CallPlan> c(new CallPlan);
-    c->n = n;
-    c->b = b;
-    c->bi = bi;
-    c->dlo = dlo;
-    c->dhi = dhi;
-    c->prec = prec;
-    c->shape = shape;
-    c->t = t;
-    c->nstages = (t + stage_kt(prec) - 1) / stage_kt(prec);
-    const int wn = shape_wn(shape);
-    std::vector<HostTile> tiles;
-    int64_t off = 0, poff = 0;
-    for (int d = dlo; d <= dhi; ++d) {
-        OrderPlan *o, *co;
-        cum_status st;
-        if (ipow64(b, d) > INT32_MAX)
-            return fail(CUM_EUNSUPPORTED, "blocks of b^d = %d^%d entries (2^31 or more) are not supported", b, d);
-        if ((st = get_order(n, b, d, &o)) || (st = get_order(n, bi, d, &co))) return st;
-        c->orders.push_back(o);
-        c->corders.push_back(co);
-        c->out_off.push_back(off);
-        c->pout_off.push_back(poff);
-        order_tiles(*co, wn, d - dlo, tiles);
-        off += o->elems;
-        poff += co->elems;
-    }
-    c->kstride = off;
-    c->stride = poff;
-    // expensive tiles first, so that the tail of each XCD's queue is short
-    std::stable_sort(tiles.begin(), tiles.end(), [](const HostTile &x, const HostTile &y) { return x.cost > y.cost; });
-    const int64_t ntiles = (int64_t)tiles.size();
-    // sample chunks (whole stages): about `target` work items (1024 fill the
-    // 256 CUs' four work-group slots once), chunks of >= 4 stages
-    int64_t want = (target + ntiles - 1) / ntiles;
-    int64_t maxch = std::max<int64_t>(1, c->nstages / 4);
-    int64_t nch = std::max<int64_t>(1, std::min(want, maxch));
-    if (nch >= 8) nch = (nch + 7) / 8 * 8;
-    c->chunk_stages = (c->nstages + nch - 1) / nch;
-    c->nchunks = (c->nstages + c->chunk_stages - 1) / c->chunk_stages;
-    // items: work-group i runs on XCD i % 8.  All items of one chunk share
-    // its stages, so a chunk goes to one XCD (8 or more chunks) or to a
-    // group of 8 / nchunks XCDs; otherwise tiles go round-robin.
+// The work items of a plan for nck sample chunks: work-group i runs on XCD
+// i % 8, and all items of one chunk share its stages, so a chunk goes to one
+// XCD (8 or more chunks) or to a group of 8 / nck XCDs; otherwise tiles go
+// round-robin.  Tiles are in cost order, so each XCD runs expensive ones first.
+static ItemSet *plan_items(CallPlan &c, int64_t nck) {
+    auto it = c.itemsets.find(nck);
+    if (it != c.itemsets.end()) return it->second.get();
     std::vector<std::vector<Item>> per_xcd(8);
-    const int64_t nck = c->nchunks;
     for (int64_t ch = 0; ch < nck; ++ch)
-        for (int64_t ti = 0; ti < ntiles; ++ti) {
+        for (int64_t ti = 0; ti < c.ntiles; ++ti) {
             int x;
             if (nck >= 8)
                 x = (int)(ch % 8);
@@ -658,20 +644,78 @@ static cum_status get_call_cfg(int n, int b, int bi, int dlo, int dhi, int prec,
         }
     size_t longest = 0;
     for (auto &v : per_xcd) longest = std::max(longest, v.size());
-    std::vector<Item> items;
-    for (size_t s = 0; s < longest; ++s)
-        for (int x = 0; x < 8; ++x) items.push_back(s < per_xcd[x].size() ? per_xcd[x][s] : Item{-1, 0, 0, 0});
-    while (!items.empty() && items.back().tile < 0) items.pop_back();
-    c->nitems = (int64_t)items.size();
-    c->items = std::move(items);
-    for (auto &h : tiles) c->tdev.push_back(h.t);
-    *out = c.get();
-    g_calls[key] = std::move(c);
+    std::unique_ptr<ItemSet> is(new ItemSet);
+    for (size_t q = 0; q < longest; ++q)
+        for (int x = 0; x < 8; ++x) is->items.push_back(q < per_xcd[x].size() ? per_xcd[x][q] : Item{-1, 0, 0, 0});
+    while (!is->items.empty() && is->items.back().tile < 0) is->items.pop_back();
+    ItemSet *r = is.get();
+    c.itemsets[nck] = std::move(is);
+    return r;
+}
+
+static cum_status get_call_cfg(int n, int b, int bi, int dlo, int dhi, int prec, int shape, int target, int64_t t,
+                               Call *out) {
+    auto key = std::make_tuple(n, b, bi, dlo, dhi, prec, shape, target);
+    auto it = g_calls.find(key);
+    CallPlan *c;
+    if (it != g_calls.end()) {
+        c = it->second.get();
+    } else {
+        std::unique_ptr<CallPlan> cp(new CallPlan);
+        cp->n = n;
+        cp->b = b;
+        cp->bi = bi;
+        cp->dlo = dlo;
+        cp->dhi = dhi;
+        cp->prec = prec;
+        cp->shape = shape;
+        cp->target = target;
+        const int wn = shape_wn(shape);
+        std::vector<HostTile> tiles;
+        int64_t off = 0, poff = 0;
+        for (int d = dlo; d <= dhi; ++d) {
+            OrderPlan *o, *co;
+            cum_status st;
+            if (ipow64(b, d) > INT32_MAX)
+                return fail(CUM_EUNSUPPORTED, "blocks of b^d = %d^%d entries (2^31 or more) are not supported", b, d);
+            if ((st = get_order(n, b, d, &o)) || (st = get_order(n, bi, d, &co))) return st;
+            cp->orders.push_back(o);
+            cp->corders.push_back(co);
+            cp->out_off.push_back(off);
+            cp->pout_off.push_back(poff);
+            order_tiles(*co, wn, d - dlo, tiles);
+            off += o->elems;
+            poff += co->elems;
+        }
+        cp->kstride = off;
+        cp->stride = poff;
+        // expensive tiles first, so that the tail of each XCD's queue is short
+        std::stable_sort(tiles.begin(), tiles.end(),
+                         [](const HostTile &x, const HostTile &y) { return x.cost > y.cost; });
+        cp->ntiles = (int64_t)tiles.size();
+        for (auto &h : tiles) cp->tdev.push_back(h.t);
+        c = cp.get();
+        g_calls[key] = std::move(cp);
+    }
+    // sample chunks (whole stages): about `target` work items (1024 fill the
+    // 256 CUs' four work-group slots once), chunks of >= 4 stages
+    Call k;
+    k.c = c;
+    k.t = t;
+    k.nstages = (t + stage_kt(prec) - 1) / stage_kt(prec);
+    const int64_t want = (target + std::max<int64_t>(c->ntiles, 1) - 1) / std::max<int64_t>(c->ntiles, 1);
+    const int64_t maxch = std::max<int64_t>(1, k.nstages / 4);
+    int64_t nch = std::max<int64_t>(1, std::min(want, maxch));
+    if (nch >= 8) nch = (nch + 7) / 8 * 8;
+    k.chunk_stages = (k.nstages + nch - 1) / nch;
+    k.nchunks = (k.nstages + k.chunk_stages - 1) / k.chunk_stages;
+    k.is = plan_items(*c, k.nchunks);
+    *out = k;
     return CUM_OK;
 }
 
 // The call plan for a shape: the tuned choice if there is one, else the defaults.
-static cum_status get_call(int n, int b, int dlo, int dhi, int prec, int64_t t, CallPlan **out) {
+static cum_status get_call(int n, int b, int dlo, int dhi, int prec, int64_t t, Call *out) {
     load_tune_file();
     auto it = g_tuned.find(std::make_tuple(n, b, dlo, dhi, prec, t));
     if (it != g_tuned.end())
@@ -726,32 +770,34 @@ static int red_lds_layout(const RedOrder *ro, int nords, bool recursion, RedArgs
 
 // The contraction of orders dlo..dhi over the staged data Xc into the
 // per-chunk partial sums, then their sum over chunks into chunk 0.
-static cum_status run_contraction(CallPlan *c, const void *Xc, double *partial, hipStream_t s) {
-    cum_status st = upload_call(*c);
+static cum_status run_contraction(const Call &k, const void *Xc, double *partial, hipStream_t s) {
+    cum_status st = upload_call(k);
     if (st) return st;
+    const CallPlan *c = k.c;
+    const int64_t nitems = (int64_t)k.is->items.size();
     MomentArgs ma;
     ma.ords = (const OrderDev *)c->ords_d.p;
     ma.tiles = (const TileDev *)c->tiles_d.p;
-    ma.items = (const Item *)c->items_d.p;
-    ma.nitems = c->nitems;
+    ma.items = (const Item *)k.is->items_d.p;
+    ma.nitems = nitems;
     ma.sets = nullptr;
     ma.set0.X = Xc;
-    ma.set0.nstages = c->nstages;
-    ma.set0.chunk_stages = c->chunk_stages;
-    ma.set0.nchunks = c->nchunks;
+    ma.set0.nstages = k.nstages;
+    ma.set0.chunk_stages = k.chunk_stages;
+    ma.set0.nchunks = k.nchunks;
     ma.set0.partial = partial;
     ma.set0.stride = c->stride;
     ma.n = c->n;
     ma.pad = 0;
-    if (c->nitems > 0)
-        HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, c->dhi, ma, (int)c->nitems, s); }));
+    if (nitems > 0)
+        HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, c->dhi, ma, (int)nitems, s); }));
     SetRed sr0;
     memset(&sr0, 0, sizeof sr0);
     sr0.partial = partial;
     sr0.stride = c->stride;
-    sr0.nchunks = c->nchunks;
-    sr0.t = c->t;
-    if (c->nchunks > 1)
+    sr0.nchunks = k.nchunks;
+    sr0.t = k.t;
+    if (k.nchunks > 1)
         HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_chunksum(nullptr, sr0, 1, c->stride, s); }));
     return CUM_OK;
 }
@@ -761,7 +807,7 @@ static cum_status run_contraction(CallPlan *c, const void *Xc, double *partial, 
 // cumulants, into outs (block storage of block size b).
 static cum_status run_finalize(CallPlan *c, double *sums, int64_t t, double *const *outs, bool recursion,
                                hipStream_t s) {
-    cum_status st = upload_call(*c);
+    cum_status st = upload_plan(*c);
     if (st) return st;
     // in pairs of orders {d, d+1}: order d needs cumulants up to d-2 only, so
     // a pair depends only on earlier pairs
@@ -808,11 +854,11 @@ static cum_status run_finalize(CallPlan *c, double *sums, int64_t t, double *con
 
 // moment contraction + reduction for orders dlo..dhi into outs (and the
 // recursion for d >= 4 when recursion is set)
-static cum_status run_orders(CallPlan *c, const void *Xc, double *partial, double *const *outs, bool recursion,
+static cum_status run_orders(const Call &k, const void *Xc, double *partial, double *const *outs, bool recursion,
                              hipStream_t s) {
     cum_status st;
-    if ((st = run_contraction(c, Xc, partial, s))) return st;
-    return run_finalize(c, partial, c->t, outs, recursion, s);
+    if ((st = run_contraction(k, Xc, partial, s))) return st;
+    return run_finalize(k.c, partial, k.t, outs, recursion, s);
 }
 
 }  // namespace cum
@@ -882,14 +928,14 @@ cum_status cum_workspace_size(int64_t t, int n, int d_max, int b, cum_prec prec,
     int64_t rows_per;
     center_groups(t, groups, rows_per);
     size_t total = staged_bytes(t, n, prec) + align_up((size_t)groups * n * 2 * 8) + align_up((size_t)n * 8);
-    CallPlan *c;
-    if ((st = get_call(n, b, 2, d_max, prec, t, &c))) return st;
-    size_t part = (size_t)c->nchunks * c->stride * 8;
+    Call k;
+    if ((st = get_call(n, b, 2, d_max, prec, t, &k))) return st;
+    size_t part = (size_t)k.nchunks * k.c->stride * 8;
     // a single-order moment call uses its own plan; cover the largest one
     for (int d = 2; d <= d_max; ++d) {
-        CallPlan *c1;
-        if ((st = get_call(n, b, d, d, prec, t, &c1))) return st;
-        part = std::max(part, (size_t)c1->nchunks * c1->stride * 8);
+        Call k1;
+        if ((st = get_call(n, b, d, d, prec, t, &k1))) return st;
+        part = std::max(part, (size_t)k1.nchunks * k1.c->stride * 8);
     }
     *bytes = total + align_up(part);
     return CUM_OK;
@@ -925,19 +971,19 @@ cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, in
     if (d < 2 || d > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d must be in 2..%d", CUM_MAX_ORDER);
     if (!Xc || !M) return fail(CUM_EINVAL, "Xc and M must not be NULL");
     std::lock_guard<std::mutex> lk(g_mu);
-    CallPlan *c;
-    if ((st = get_call(n, b, d, d, prec, t, &c))) return st;
+    Call k;
+    if ((st = get_call(n, b, d, d, prec, t, &k))) return st;
     const size_t xbytes = staged_bytes(t, n, prec);
-    const size_t need = xbytes + align_up((size_t)c->nchunks * c->stride * 8);
+    const size_t need = xbytes + align_up((size_t)k.nchunks * k.c->stride * 8);
     if (!ws || ws_bytes < need) return fail(CUM_ENOMEM, "moment_blocks needs %zu workspace bytes", need);
-    if ((st = upload_call(*c))) return st;
+    if ((st = upload_call(k))) return st;
     hipStream_t s = (hipStream_t)stream;
     char *Xst = (char *)ws;
     HIP_TRY(timed(CUM_KIND_CENTER, s, [&] {
         return launch_stage(Xc, t, n, n, nullptr, Xst, prec, false, prec == CUM_F64, s);
     }));
     double *outs[1] = {M};
-    return run_orders(c, Xst, (double *)(Xst + xbytes), outs, false, s);
+    return run_orders(k, Xst, (double *)(Xst + xbytes), outs, false, s);
 }
 
 cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
@@ -950,15 +996,15 @@ cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_m
     for (int d = 2; d <= d_max; ++d)
         if (!kappa[d - 2]) return fail(CUM_EINVAL, "kappa[%d] is NULL", d - 2);
     std::lock_guard<std::mutex> lk(g_mu);
-    CallPlan *c;
-    if ((st = get_call(n, b, 2, d_max, prec, t, &c))) return st;
+    Call k;
+    if ((st = get_call(n, b, 2, d_max, prec, t, &k))) return st;
     int groups;
     int64_t rows_per;
     center_groups(t, groups, rows_per);
     const size_t xbytes = staged_bytes(t, n, prec);
     const size_t cbytes = align_up((size_t)groups * n * 2 * 8);
     const size_t mbytes = align_up((size_t)n * 8);
-    const size_t pbytes = align_up((size_t)c->nchunks * c->stride * 8);
+    const size_t pbytes = align_up((size_t)k.nchunks * k.c->stride * 8);
     const size_t need = xbytes + cbytes + mbytes + pbytes;
     if (!ws || ws_bytes < need) return fail(CUM_ENOMEM, "cumulants needs %zu workspace bytes (got %zu)", need, ws_bytes);
     char *w = (char *)ws;
@@ -968,10 +1014,10 @@ cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_m
     double *partial = (double *)(w + xbytes + cbytes + mbytes);
     hipStream_t s = (hipStream_t)stream;
     double *mu = mean ? mean : mtmp;
-    if ((st = upload_call(*c))) return st;
+    if ((st = upload_call(k))) return st;
     if ((st = center_impl(X, t, n, ldx, prec, mu, nullptr, cw, cbytes, s))) return st;
     HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, mu, Xst, prec, true, true, s); }));
-    return run_orders(c, Xst, partial, kappa, true, s);
+    return run_orders(k, Xst, partial, kappa, true, s);
 }
 
 cum_status cum_unfold(const double *blocks, int n, int d, int b, double *dense, void *stream) {
@@ -1193,24 +1239,22 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     hipStream_t s = (hipStream_t)stream;
     const int shapes[] = {TS_1x1, TS_1x2};
     const int targets[] = {1024, 2048, 4096, 8192, 16384};
-    std::vector<CallPlan *> cands;
-    std::vector<int> cand_target;
+    std::vector<Call> cands;
     size_t part_max = 0;
     for (int bi : inner_candidates(b))
         for (int sh : shapes)
             for (int tg : targets) {
-                CallPlan *c;
-                if ((st = get_call_cfg(n, b, bi, 2, d_max, prec, sh, tg, t, &c))) return st;
-                if ((st = upload_call(*c))) return st;
-                cands.push_back(c);
-                cand_target.push_back(tg);
-                part_max = std::max(part_max, align_up((size_t)c->nchunks * c->stride * 8));
+                Call k;
+                if ((st = get_call_cfg(n, b, bi, 2, d_max, prec, sh, tg, t, &k))) return st;
+                if ((st = upload_call(k))) return st;
+                cands.push_back(k);
+                part_max = std::max(part_max, align_up((size_t)k.nchunks * k.c->stride * 8));
             }
     int groups;
     int64_t rows_per;
     center_groups(t, groups, rows_per);
     const size_t xbytes = staged_bytes(t, n, prec), cbytes = align_up((size_t)groups * n * 2 * 8);
-    const size_t mbytes = align_up((size_t)n * 8), kbytes = align_up((size_t)cands[0]->kstride * 8);
+    const size_t mbytes = align_up((size_t)n * 8), kbytes = align_up((size_t)cands[0].c->kstride * 8);
     DevBuf ws;
     HIP_TRY(hipMalloc(&ws.p, xbytes + cbytes + mbytes + kbytes + part_max));
     char *w = (char *)ws.p;
@@ -1218,7 +1262,7 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     double *mu = (double *)(w + xbytes + cbytes), *kap = (double *)(w + xbytes + cbytes + mbytes);
     double *partial = (double *)(w + xbytes + cbytes + mbytes + kbytes);
     double *outs[CUM_MAX_ORDER];
-    for (int d = 2; d <= d_max; ++d) outs[d - 2] = kap + cands[0]->out_off[d - 2];
+    for (int d = 2; d <= d_max; ++d) outs[d - 2] = kap + cands[0].c->out_off[d - 2];
     if ((st = center_impl(X, t, n, ldx, prec, mu, nullptr, cw, cbytes, s))) return st;
     HIP_TRY(launch_stage(X, t, n, ldx, mu, Xst, prec, true, true, s));
     const bool was_timing = g_timing;
@@ -1227,8 +1271,8 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best_ms = 1e30f;
-    CallPlan *best_c = nullptr;
-    for (CallPlan *c : cands) {
+    const CallPlan *best_c = nullptr;
+    for (const Call &c : cands) {
         float cand_ms = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
             HIP_TRY(hipEventRecord(e0, s));
@@ -1242,7 +1286,7 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
         if (st) break;
         if (cand_ms < best_ms) {
             best_ms = cand_ms;
-            best_c = c;
+            best_c = c.c;
         }
     }
     (void)hipEventDestroy(e0);
@@ -1250,9 +1294,7 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     g_timing = was_timing;
     if (st) return st;
     HIP_TRY(hipStreamSynchronize(s));
-    int best_target = 0;
-    for (size_t i = 0; i < cands.size(); ++i)
-        if (cands[i] == best_c) best_target = cand_target[i];
+    const int best_target = best_c->target;
     g_tuned[std::make_tuple(n, b, 2, d_max, (int)prec, t)] = Tuning{best_c->shape, best_target, best_c->bi};
     save_tune_file();
     if (best) {
@@ -1768,15 +1810,15 @@ cum_status cum_stream_update(cum_stream *p, const double *X, int64_t t, int64_t 
     hipStream_t s = (hipStream_t)stream;
     const int n = p->n;
     // the contraction fills the layout of block size 1 (each sorted tuple once)
-    CallPlan *c;
-    if ((st = get_call_cfg(n, p->b, 1, 2, p->d_max, p->prec, default_shape(p->prec), DEFAULT_TARGET, t, &c)))
+    Call k;
+    if ((st = get_call_cfg(n, p->b, 1, 2, p->d_max, p->prec, default_shape(p->prec), DEFAULT_TARGET, t, &k)))
         return st;
-    if ((st = upload_call(*c))) return st;
+    if ((st = upload_call(k))) return st;
     int groups;
     int64_t rows_per;
     center_groups(t, groups, rows_per);
     const size_t xbytes = staged_bytes(t, n, p->prec), cbytes = align_up((size_t)groups * n * 2 * 8);
-    const size_t need = xbytes + cbytes + align_up((size_t)c->nchunks * c->stride * 8);
+    const size_t need = xbytes + cbytes + align_up((size_t)k.nchunks * k.c->stride * 8);
     if (need > p->ws_bytes) {
         // the old workspace may still be read by work queued on the stream
         HIP_TRY(hipStreamSynchronize(s));
@@ -1802,11 +1844,11 @@ cum_status cum_stream_update(cum_stream *p, const double *X, int64_t t, int64_t 
     }));
     // the batch's sums of products of x - c, added into (or taken from) the window's
     HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, shift, Xst, p->prec, true, true, s); }));
-    if ((st = run_contraction(c, Xst, partial, s))) return st;
+    if ((st = run_contraction(k, Xst, partial, s))) return st;
     HIP_TRY(timed(CUM_KIND_REDUCE, s,
                   [&] { return launch_axpy((double *)p->sums_d.p, partial, (double)sign, p->stride, s); }));
     p->t += sign * t;
-    p->last = c;
+    p->last = k.c;
     return CUM_OK;
 }
 
