@@ -47,6 +47,24 @@ def alg_flops(pc, t, n, d_max, b):
     return sum(2.0 * t * pc.layout(n, d, b)["elems"] for d in range(2, d_max + 1))
 
 
+HBM_PEAK_GBS = 8000.0
+
+
+def finalisation_record(pc, kinds, steps, t, n, d_max, b, prec):
+    """The chunk sum and the finalisation (M = S/t and the recursion): HBM
+    bound.  Algorithmic bytes per step: the chunk sum reads every chunk's sums
+    and writes one (when there is more than one chunk); the finalisation reads
+    one sum and writes one cumulant per stored entry."""
+    info = pc.plan_info(t, n, d_max, b, prec)
+    nbytes = 16.0 * info["stored_entries"]
+    if info["nchunks"] > 1:
+        nbytes += 8.0 * (info["nchunks"] + 1) * info["partial_entries"]
+    ms = kinds["reduce"][0] / steps
+    gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
+    return {"ms_per_step": ms, "bytes_per_step": nbytes, "GB/s": gbs,
+            "frac_of_hbm": gbs / HBM_PEAK_GBS if gbs else None, "plan": info}
+
+
 def time_path(torch, pc, Xd, d_max, b, prec, steps, warmup, tune):
     t, n = Xd.shape
     tuned = pc.autotune(Xd, d_max, b, prec) if tune else None
@@ -241,7 +259,8 @@ def bench_workloads(torch, pc, orc, steps, tune):
             per_launch = kinds["moment"][0] / max(kinds["moment"][1], 1)
             res[p] = {"ms_per_step": wall * 1e3, "tflops": flops / wall / 1e12, "ms_per_step_pct": pct,
                       "moment_tflops": kflops / (per_launch * 1e-3) / 1e12,
-                      "mfma_frac": kflops / (per_launch * 1e-3) / 1e12 / PEAK[p], "config": cfg}
+                      "mfma_frac": kflops / (per_launch * 1e-3) / 1e12 / PEAK[p], "config": cfg,
+                      "finalisation": finalisation_record(pc, kinds, steps, t, n, d_max, b, p)}
             kap[p] = {d: o[d].cpu().numpy() for d in o}
             log(f"  {p}: {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s")
         errs = sampled_errors(orc, pc, X, kap, n, d_max, b, count=40, seed=11)
@@ -336,6 +355,7 @@ def main():
                   "moment_flop_per_launch": kflops,
                   "mfma_frac": achieved * PRODUCTS[p] / PEAK[p],
                   "kernel_ms": {k: v[0] / args.steps for k, v in kinds.items() if v[1]},
+                  "finalisation": finalisation_record(pc, kinds, args.steps, t, n, d_max, b, p),
                   "tuning": tuned, "config": cfg}
         kappa[p] = {d: out[d].cpu().numpy() for d in out}
         log(f"  {p}: {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s; "

@@ -187,6 +187,17 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
  * shape, target_items < 1 or inner_b outside 1..b. */
 cum_status cum_set_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, const cum_tuning *tune /* host */);
 
+/* Host only.  How cum_cumulants(t, n, d_max, b, prec) splits its work in
+ * its current configuration (tuned, else the defaults). */
+typedef struct {
+    int64_t nchunks;          /* sample chunks (each a run of whole stages)       */
+    int64_t work_items;       /* (tile, chunk) items of the contraction launch    */
+    int64_t tiles;            /* work-group tiles over all orders                 */
+    int64_t partial_entries;  /* sums per chunk (layout of the inner block size)  */
+    int64_t stored_entries;   /* outputs of orders 2..d_max in block storage      */
+} cum_plan_info;
+cum_status cum_get_plan_info(int64_t t, int n, int d_max, int b, cum_prec prec, cum_plan_info *info /* host out */);
+
 /* Host only.  The configuration cum_cumulants(t, n, d_max, b, prec) uses:
  * the tuned one if there is one, else the defaults (ms = 0). */
 cum_status cum_get_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, cum_tuning *tune /* host out */);

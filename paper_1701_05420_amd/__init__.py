@@ -31,12 +31,17 @@ MAX_ORDER = 10
 EXPORTS = [
     "cum_layout_query", "cum_workspace_size", "cum_center", "cum_moment_blocks", "cum_cumulants", "cum_unfold",
     "cum_stored_offset", "cum_batch_create", "cum_batch_run", "cum_batch_timestamps", "cum_batch_destroy",
-    "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning", "cum_get_tuning",
+    "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning", "cum_get_tuning", "cum_get_plan_info",
     "cum_batch_autotune", "cum_stream_create", "cum_stream_update", "cum_stream_cumulants", "cum_stream_cumulants_moebius",
     "cum_stream_count",
     "cum_stream_reset", "cum_stream_destroy", "cum_status_str", "cum_last_error",
 ]
 SHAPES = {"32x32": 0, "32x64": 2}
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("nchunks", ctypes.c_int64), ("work_items", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("partial_entries", ctypes.c_int64), ("stored_entries", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):
@@ -69,6 +74,7 @@ _lib.cum_timing_enable.argtypes = [_I]
 _lib.cum_autotune.argtypes = [_VP, _I64, _I, _I64, _I, _I, _I, _VP, ctypes.POINTER(Tuning)]
 _lib.cum_set_tuning.argtypes = [_I64, _I, _I, _I, _I, ctypes.POINTER(Tuning)]
 _lib.cum_get_tuning.argtypes = [_I64, _I, _I, _I, _I, ctypes.POINTER(Tuning)]
+_lib.cum_get_plan_info.argtypes = [_I64, _I, _I, _I, _I, ctypes.POINTER(PlanInfo)]
 _lib.cum_batch_autotune.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(Tuning)]
 _lib.cum_stream_create.argtypes = [_I, _I, _I, _I, _VP, ctypes.POINTER(_VP)]
 _lib.cum_stream_update.argtypes = [_VP, _VP, _I64, _I64, _I, _VP]
@@ -145,6 +151,13 @@ def get_tuning(t: int, n: int, d_max: int, b: int, prec) -> dict:
     out = Tuning()
     _check(_lib.cum_get_tuning(t, n, d_max, b, _prec(prec), ctypes.byref(out)))
     return {"shape": out.shape, "target_items": out.target_items, "inner_b": out.inner_b}
+
+
+def plan_info(t: int, n: int, d_max: int, b: int, prec) -> dict:
+    """How cumulants() splits the work for this shape in its current configuration."""
+    out = PlanInfo()
+    _check(_lib.cum_get_plan_info(t, n, d_max, b, _prec(prec), ctypes.byref(out)))
+    return {f: getattr(out, f) for f, _ in PlanInfo._fields_}
 
 
 def set_tuning(t: int, n: int, d_max: int, b: int, prec, shape=None, target_items=4096, inner_b=1) -> None:

@@ -1201,6 +1201,22 @@ cum_status cum_set_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, con
     return CUM_OK;
 }
 
+cum_status cum_get_plan_info(int64_t t, int n, int d_max, int b, cum_prec prec, cum_plan_info *info) {
+    cum_status st;
+    if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;
+    if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
+    if (!info) return fail(CUM_EINVAL, "info is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    Call k;
+    if ((st = get_call(n, b, 2, d_max, prec, t, &k))) return st;
+    info->nchunks = k.nchunks;
+    info->work_items = (int64_t)k.is->items.size();
+    info->tiles = k.c->ntiles;
+    info->partial_entries = k.c->stride;
+    info->stored_entries = k.c->kstride;
+    return CUM_OK;
+}
+
 cum_status cum_get_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, cum_tuning *tune) {
     cum_status st;
     if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;

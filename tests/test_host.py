@@ -179,3 +179,20 @@ def test_tune_file_is_read_and_bad_lines_skipped(tmp_path):
     assert out[0] == "{'shape': 2, 'target_items': 4096, 'inner_b': 2}"
     for line in out[1:]:
         assert line == "{'shape': 0, 'target_items': 4096, 'inner_b': 1}"
+
+
+def test_plan_info_counts(pc):
+    """The split of a call: partial sums in the inner layout (each sorted
+    variable tuple once at inner block size 1), outputs in block storage, and
+    one work item per (tile, chunk) at most."""
+    shape = (100_000, 48, 4, 4, "f32")
+    pc.set_tuning(*shape, None)
+    info = pc.plan_info(*shape)
+    assert info["partial_entries"] == sum(math.comb(48 + d - 1, d) for d in range(2, 5))
+    assert info["stored_entries"] == sum(pc.layout(48, d, 4)["elems"] for d in range(2, 5))
+    assert 1 <= info["nchunks"] <= 100_000 // 64 // 4
+    assert info["work_items"] <= info["tiles"] * info["nchunks"]
+    pc.set_tuning(*shape, "32x32", 1024, inner_b=4)
+    info4 = pc.plan_info(*shape)
+    assert info4["partial_entries"] == info4["stored_entries"]
+    pc.set_tuning(*shape, None)
