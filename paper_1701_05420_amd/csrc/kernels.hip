@@ -270,22 +270,22 @@ struct PT;
 template <>
 struct PT<P_F64> {
     typedef double T;
-    enum { KT = 32, KTP = 40, FLUSH_STAGES = 0 };
+    enum { KT = 32, KTP = 40 };
 };
 template <>
 struct PT<P_F32> {
     typedef float T;
-    enum { KT = 64, KTP = 80, FLUSH_STAGES = 1 };
+    enum { KT = 64, KTP = 80 };
 };
 template <>
 struct PT<P_BF16X2> {
     typedef float T;
-    enum { KT = 64, KTP = 68, FLUSH_STAGES = 1 };
+    enum { KT = 64, KTP = 68 };
 };
 template <>
 struct PT<P_BF16X3> {
     typedef float T;
-    enum { KT = 64, KTP = 68, FLUSH_STAGES = 1 };
+    enum { KT = 64, KTP = 68 };
 };
 
 int lds_bytes_moment(int prec, int n) { return 2 * (n + 1) * stage_pitch(prec) * stage_esize(prec); }
