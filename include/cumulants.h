@@ -13,7 +13,10 @@
  *   - the cumulants c_2..c_dmax by the recursion of Section 3.2 (eq. cum_r;
  *     Alg. 4 and Alg. 5): c_2 = m_2, c_3 = m_3, and for d >= 4 the central
  *     moment minus the sum over partitions of the d positions into >= 2
- *     parts of size >= 2 of products of lower-order cumulants.
+ *     parts of size >= 2 of products of lower-order cumulants,
+ *   - the same for many datasets in one graph-captured run (cum_batch_*) and
+ *     for a sliding window of samples (cum_stream_*, with the general
+ *     formula of Section 5.3 as a second finalisation).
  * Normalisation is 1/t throughout (plug-in estimator, so c_2 is the biased
  * covariance).
  *
@@ -24,8 +27,10 @@
  * - Pointers are DEVICE pointers unless marked (host).  The caller owns every
  *   buffer; the library never frees caller memory.  Scratch memory is the
  *   caller's workspace, sized by cum_workspace_size().  The library keeps
- *   small per-shape index tables of its own in device memory (allocated on
- *   first use of a shape, freed at process exit).
+ *   small index tables of its own in device memory, one set per
+ *   configuration (n, b, orders, precision, launch shape; not per sample
+ *   count), allocated on first use and freed at process exit.  Batch plans
+ *   and streams own their device state until destroyed.
  * - stream is a hipStream_t passed as void* (NULL = the default stream).
  *   Work is enqueued asynchronously on it; outputs are valid once the stream
  *   has reached that point.  Calls that share a workspace must not overlap.
