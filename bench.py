@@ -270,6 +270,49 @@ def bench_workloads(torch, pc, orc, steps, tune):
     return out
 
 
+def bench_small(torch, pc, steps):
+    """The launch-bound workload (n = 16, t = 5000, d <= 4, b = 2, FP64 path):
+    per-call latency of eager calls and of replays of a HIP graph captured
+    from one call."""
+    import workloads
+
+    name = "t-wishart-n16-t5000"
+    w = workloads.WORKLOADS[name]
+    n, b, d_max, t = w["n"], w["b"], w["d_max"], w["t"]
+    Xd = torch.from_numpy(workloads.generate(name)).cuda()
+    out = {d: torch.empty(pc.layout(n, d, b)["elems"], dtype=torch.float64, device="cuda")
+           for d in range(2, d_max + 1)}
+    ws = torch.empty(pc.workspace_size(t, n, d_max, b, "f64"), dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        pc.cumulants(Xd, d_max, b, "f64", ws=ws, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pc.cumulants(Xd, d_max, b, "f64", ws=ws, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    eager_us = e0.elapsed_time(e1) / steps * 1e3
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            pc.cumulants(Xd, d_max, b, "f64", ws=ws, out=out, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_us = e0.elapsed_time(e1) / steps * 1e3
+    flops = alg_flops(pc, t, n, d_max, b)
+    return {"workload": name, "prec": "f64", "eager_us_per_call": eager_us, "graph_us_per_replay": graph_us,
+            "eff_tflops_graph": flops / (graph_us * 1e-6) / 1e12}
+
+
 def traffic_record(prec, workload):
     """HBM bytes per moment launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
@@ -399,6 +442,9 @@ def main():
             f"{line['batched']['per_dataset_calls']['datasets_per_s']:.0f} with one call per dataset")
     if not args.no_workloads:
         line["workloads"] = bench_workloads(torch, pc, orc, max(5, args.steps // 2), not args.no_tune)
+        line["small"] = bench_small(torch, pc, max(50, args.steps * 5))
+        log(f"  small workload: {line['small']['eager_us_per_call']:.1f} us per eager call, "
+            f"{line['small']['graph_us_per_replay']:.1f} us per graph replay")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(orc, X, n, d_max, b, pc, args.cpu_seconds)

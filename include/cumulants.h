@@ -133,7 +133,10 @@ cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, in
  *   kappa  (host) array of d_max-1 device pointers; kappa[d-2] receives c_d
  *          in block storage (cum_layout(n, d, b).elems FP64 each)
  * The data are centred in FP64; only the moment contraction runs in prec.
- * Requires t >= 1, 1 <= b <= n, 2 <= d_max <= CUM_MAX_ORDER. */
+ * Requires t >= 1, 1 <= b <= n, 2 <= d_max <= CUM_MAX_ORDER.  The first call
+ * of a configuration builds its tables (device allocations); later calls
+ * allocate nothing and enqueue only kernels, so they may be captured in a
+ * HIP graph. */
 cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
                          double *mean, double *const *kappa /* host array */, void *ws, size_t ws_bytes,
                          void *stream);

@@ -254,3 +254,39 @@ def test_autotune_and_tuned_configs(dev, orc):
         say(f"autotune {prec}: {best}")
         assert best["shape"] in (0, 2) and best["ms"] > 0 and 1 <= best["inner_b"] <= 4
         pc.set_tuning(30_000, 24, 5, 4, prec, None)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graph_capture_replays(dev, orc, prec):
+    """After one call of a shape, cum_cumulants allocates nothing and issues
+    only kernels, so it can be captured in a HIP graph: every replay (with
+    eager work and synchronisations between replays) gives the eager bits."""
+    torch, pc = dev
+    n, b, dmax, t = 16, 2, 4, 5000
+    X = workloads.generate("t-wishart-n16-t5000")
+    Xd = torch.from_numpy(X).cuda()
+    ws = torch.empty(pc.workspace_size(t, n, dmax, b, prec), dtype=torch.uint8, device="cuda")
+    out = {d: torch.empty(pc.layout(n, d, b)["elems"], dtype=torch.float64, device="cuda") for d in range(2, dmax + 1)}
+    mean = torch.empty(n, dtype=torch.float64, device="cuda")
+    pc.cumulants(Xd, dmax, b, prec, ws=ws, out=out)  # tables for the shape exist from here on
+    torch.cuda.synchronize()
+    ref = {d: out[d].clone() for d in out}
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            pc.cumulants(Xd, dmax, b, prec, ws=ws, out=out, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(4):
+        for d in out:
+            out[d].fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        for d in out:
+            assert torch.equal(out[d], ref[d]), (rep, d)
+        _, _ = pc.cumulants(Xd[: t // 2], dmax, b, prec)  # eager work in between
+        torch.cuda.synchronize()
+    _, OK = orc.cumulants_dense(X, dmax)
+    for d in out:
+        assert rel(out[d].cpu().numpy(), orc.fold(OK[d], b)) <= TOL[prec]
