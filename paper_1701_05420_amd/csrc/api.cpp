@@ -768,9 +768,15 @@ static int red_lds_layout(const RedOrder *ro, int nords, bool recursion, RedArgs
     return ra.parts_off + (ra.parts_lds ? (int)(parts * 4) : 0);
 }
 
+// Partial sums up to this many (all chunks) are left for the finalisation to
+// add up: a separate chunk-sum launch costs more than it saves there.
+constexpr int64_t SMALL_PARTIALS = (int64_t)1 << 20;
+
 // The contraction of orders dlo..dhi over the staged data Xc into the
-// per-chunk partial sums, then their sum over chunks into chunk 0.
-static cum_status run_contraction(const Call &k, const void *Xc, double *partial, hipStream_t s) {
+// per-chunk partial sums, then (if always_sum, or the partial sums are not
+// small) their sum over chunks into chunk 0.  *summed tells which.
+static cum_status run_contraction(const Call &k, const void *Xc, double *partial, bool always_sum, bool *summed,
+                                  hipStream_t s) {
     cum_status st = upload_call(k);
     if (st) return st;
     const CallPlan *c = k.c;
@@ -791,22 +797,24 @@ static cum_status run_contraction(const Call &k, const void *Xc, double *partial
     ma.pad = 0;
     if (nitems > 0)
         HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, c->dhi, ma, (int)nitems, s); }));
-    SetRed sr0;
-    memset(&sr0, 0, sizeof sr0);
-    sr0.partial = partial;
-    sr0.stride = c->stride;
-    sr0.nchunks = k.nchunks;
-    sr0.t = k.t;
-    if (k.nchunks > 1)
+    *summed = k.nchunks == 1 || always_sum || k.nchunks * c->stride > SMALL_PARTIALS;
+    if (k.nchunks > 1 && *summed) {
+        SetRed sr0;
+        memset(&sr0, 0, sizeof sr0);
+        sr0.partial = partial;
+        sr0.stride = c->stride;
+        sr0.nchunks = k.nchunks;
+        sr0.t = k.t;
         HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_chunksum(nullptr, sr0, 1, c->stride, s); }));
+    }
     return CUM_OK;
 }
 
-// Finalisation of orders dlo..dhi from summed moment sums S (one chunk, in
-// the call's partial-sum layout): M = S / t and, with recursion, the
-// cumulants, into outs (block storage of block size b).
-static cum_status run_finalize(CallPlan *c, double *sums, int64_t t, double *const *outs, bool recursion,
-                               hipStream_t s) {
+// Finalisation of orders dlo..dhi from moment sums S (nchunks chunks in the
+// call's partial-sum layout, added in chunk order): M = S / t and, with
+// recursion, the cumulants, into outs (block storage of block size b).
+static cum_status run_finalize(CallPlan *c, double *sums, int64_t nchunks, int64_t t, double *const *outs,
+                               bool recursion, hipStream_t s) {
     cum_status st = upload_plan(*c);
     if (st) return st;
     // in pairs of orders {d, d+1}: order d needs cumulants up to d-2 only, so
@@ -820,13 +828,13 @@ static cum_status run_finalize(CallPlan *c, double *sums, int64_t t, double *con
         ra.nords = (d + 1 <= c->dhi) ? 2 : 1;
         ra.d0 = d;
         ra.recursion = recursion ? 1 : 0;
-        ra.presummed = 1;
+        ra.presummed = 0;
         ra.nb0 = c->red[i0].nblocks;
         ra.nbtot = ra.nb0 + (ra.nords == 2 ? c->red[i0 + 1].nblocks : 0);
         ra.sets = nullptr;
         ra.set0.partial = sums;
         ra.set0.stride = c->stride;
-        ra.set0.nchunks = 1;
+        ra.set0.nchunks = nchunks;
         ra.set0.t = t;
         for (int k = 0; k < MAXD - 1; ++k) ra.set0.kappa[k] = nullptr;
         for (int dd = c->dlo; dd <= c->dhi; ++dd) ra.set0.kappa[dd - 2] = outs[dd - c->dlo];
@@ -857,8 +865,9 @@ static cum_status run_finalize(CallPlan *c, double *sums, int64_t t, double *con
 static cum_status run_orders(const Call &k, const void *Xc, double *partial, double *const *outs, bool recursion,
                              hipStream_t s) {
     cum_status st;
-    if ((st = run_contraction(k, Xc, partial, s))) return st;
-    return run_finalize(k.c, partial, k.t, outs, recursion, s);
+    bool summed;
+    if ((st = run_contraction(k, Xc, partial, false, &summed, s))) return st;
+    return run_finalize(k.c, partial, summed ? 1 : k.nchunks, k.t, outs, recursion, s);
 }
 
 }  // namespace cum
@@ -1860,7 +1869,8 @@ cum_status cum_stream_update(cum_stream *p, const double *X, int64_t t, int64_t 
     }));
     // the batch's sums of products of x - c, added into (or taken from) the window's
     HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, shift, Xst, p->prec, true, true, s); }));
-    if ((st = run_contraction(k, Xst, partial, s))) return st;
+    bool summed;
+    if ((st = run_contraction(k, Xst, partial, true, &summed, s))) return st;
     HIP_TRY(timed(CUM_KIND_REDUCE, s,
                   [&] { return launch_axpy((double *)p->sums_d.p, partial, (double)sign, p->stride, s); }));
     p->t += sign * t;
@@ -1898,7 +1908,7 @@ cum_status cum_stream_cumulants(cum_stream *p, double *mean, double *const *kapp
         HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_recentre(ra, s); }));
     }
     // the central moments are already divided by t
-    return run_finalize(p->last, (double *)p->central_d.p, 1, kappa, true, s);
+    return run_finalize(p->last, (double *)p->central_d.p, 1, 1, kappa, true, s);
 }
 
 // device tables of all_partitions, per order
@@ -1963,7 +1973,7 @@ cum_status cum_stream_cumulants_moebius(cum_stream *p, double *mean, double *con
         HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_moebius(ma, s); }));
     }
     // expand each tuple's cumulant to every stored copy (t = 1: no division)
-    return run_finalize(p->last, (double *)p->central_d.p, 1, kappa, false, s);
+    return run_finalize(p->last, (double *)p->central_d.p, 1, 1, kappa, false, s);
 }
 
 cum_status cum_stream_count(cum_stream *p, int64_t *t) {
