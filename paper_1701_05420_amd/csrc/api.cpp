@@ -845,14 +845,16 @@ static cum_status run_finalize(CallPlan *c, double *sums, int64_t nchunks, int64
             ra.nbtot = ra.nb0;
         }
         const int lds = red_lds_layout(&c->red[i0], ra.nords, recursion, ra);
-        HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(ra, 1, lds, s); }));
+        const int be0 = (int)ipow64(c->red[i0].b, d);
+        HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(ra, 1, lds, be0, s); }));
         if (!recursion) {
             for (int dd = d + 1; dd <= c->dhi; ++dd) {
                 RedArgs rb = ra;
                 rb.ords = red_d + (dd - c->dlo);
                 rb.d0 = dd;
                 rb.nb0 = rb.nbtot = c->red[dd - c->dlo].nblocks;
-                HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(rb, 1, 0, s); }));
+                const int be = (int)ipow64(c->red[dd - c->dlo].b, dd);
+                HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(rb, 1, 0, be, s); }));
             }
             break;
         }
@@ -1542,7 +1544,7 @@ static cum_status batch_enqueue(cum_batch &p, hipStream_t s) {
         ra.nbtot = ra.nb0 + (ra.nords == 2 ? p.red[i0 + 1].nblocks : 0);
         ra.sets = (const SetRed *)p.setred_d.p;
         const int lds = red_lds_layout(&p.red[i0], ra.nords, true, ra);
-        HIP_TRY(launch_reduce(ra, p.nsets, lds, s));
+        HIP_TRY(launch_reduce(ra, p.nsets, lds, (int)ipow64(p.b, d), s));
     }
     return CUM_OK;
 }

@@ -738,7 +738,7 @@ __device__ __forceinline__ double *kappa_of(const SetRed &sr, int m) {
     }
 }
 
-template <int D>
+template <int D, int NT>
 __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder &ro, const SetRed &sr, int64_t B,
                                                char *dyn, int *tup) {
     constexpr int PARTS = D / 2;  // parts per partition slot
@@ -759,12 +759,12 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
     __syncthreads();  // the previous block's readers are done with the LDS tables
     if (tid < D) tup[tid] = gmem(ro.tuples)[B * D + tid];
     if (parts_in_lds)
-        for (int i = tid; i < ro.npart * PARTS; i += 256) parts_l[i] = parts_g[i];
+        for (int i = tid; i < ro.npart * PARTS; i += NT) parts_l[i] = parts_g[i];
     __syncthreads();
     if (rec) {
         // block offset of j_S in the order-|S| layout: the rank of the sorted
         // tuple j_S (sum of the hockey-stick rank terms) times b^|S|
-        for (int s = tid; s < ro.ns; s += 256) {
+        for (int s = tid; s < ro.ns; s += NT) {
             const unsigned mask = gmem(ro.smask)[s];
             const int m = __popc(mask);
             int64_t rank = 0, bm = 1;
@@ -788,7 +788,7 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
 #pragma unroll
         for (int m = 2; m <= D - 2; ++m) {
             const CUM_GLOBAL double *kp = gmem(sr.kappa[m - 2]);
-            for (int e = ro.mstart[m - 2] + tid; e < ro.mstart[m - 1]; e += 256) {
+            for (int e = ro.mstart[m - 2] + tid; e < ro.mstart[m - 1]; e += NT) {
                 const int g = gmem(ro.gmap)[e];
                 sub[e] = kp[base[g & 1023] + (g >> 10)];
             }
@@ -808,12 +808,12 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
 #pragma unroll
     for (int k = 0; k + 1 < D; ++k) need_sort |= tup[k] == tup[k + 1];
 
-    for (unsigned o0 = tid; o0 < be; o0 += 256 * EPT) {
+    for (unsigned o0 = tid; o0 < be; o0 += NT * EPT) {
         int r[EPT][D];  // in-block digits, first position most significant
         double M[EPT];
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
-            unsigned oo = o0 + 256u * q;
+            unsigned oo = o0 + (unsigned)NT * q;
             const bool valid = oo < be;
             if (!valid) oo = 0;
 #pragma unroll
@@ -821,7 +821,7 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
                 r[q][k] = (int)(oo % b);
                 oo /= b;
             }
-            int64_t poff = (int64_t)B * be + o0 + 256u * q;
+            int64_t poff = (int64_t)B * be + o0 + (unsigned)NT * q;
             bool pad = !valid;
             if (canon && valid) {
                 int u[D];
@@ -921,15 +921,17 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
             recursion(std::false_type());
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
-            const unsigned o = o0 + 256u * q;
+            const unsigned o = o0 + (unsigned)NT * q;
             if (o < be) out[B * be + o] = M[q];
         }
     }
     if (sr.stamp && tid == 0) atomicMax(sr.stamp, (unsigned long long)wall_clock64());
 }
 
-template <int D0>
-__global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
+// NT threads per work-group: 256, or one wave (64) when the blocks are small
+// (b^d <= 256), so that more blocks are in flight per compute unit.
+template <int D0, int NT>
+__global__ __launch_bounds__(NT) void reduce_kernel(RedArgs a) {
     extern __shared__ __align__(16) char dyn[];
     __shared__ int tup[MAXD];
     SetRed sr = a.set0;
@@ -937,11 +939,11 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs a) {
     for (int64_t gb = blockIdx.x; gb < a.nbtot; gb += gridDim.x) {
         if (gb < a.nb0) {
             const RedOrder ro = a.ords[0];
-            finalize_block<D0>(a, ro, sr, gb, dyn, tup);
+            finalize_block<D0, NT>(a, ro, sr, gb, dyn, tup);
         } else {
             if constexpr (D0 < MAXD) {
                 const RedOrder ro = a.ords[1];
-                finalize_block<D0 + 1>(a, ro, sr, gb - a.nb0, dyn, tup);
+                finalize_block<D0 + 1, NT>(a, ro, sr, gb - a.nb0, dyn, tup);
             }
         }
     }
@@ -979,22 +981,31 @@ hipError_t launch_chunksum(const SetRed *sets, const SetRed &set0, int nsets, in
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, hipStream_t s) {
+template <int NT>
+static void launch_reduce_nt(const RedArgs &a, dim3 grid, int lds_bytes, hipStream_t s) {
+    const dim3 block(NT);
+    switch (a.d0) {
+        case 2: hipLaunchKernelGGL((reduce_kernel<2, NT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 3: hipLaunchKernelGGL((reduce_kernel<3, NT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 4: hipLaunchKernelGGL((reduce_kernel<4, NT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 5: hipLaunchKernelGGL((reduce_kernel<5, NT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 6: hipLaunchKernelGGL((reduce_kernel<6, NT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 7: hipLaunchKernelGGL((reduce_kernel<7, NT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 8: hipLaunchKernelGGL((reduce_kernel<8, NT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 9: hipLaunchKernelGGL((reduce_kernel<9, NT>), grid, block, (size_t)lds_bytes, s, a); break;
+        default: hipLaunchKernelGGL((reduce_kernel<10, NT>), grid, block, (size_t)lds_bytes, s, a); break;
+    }
+}
+
+hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, int block_elems, hipStream_t s) {
+    if (a.d0 < 2 || a.d0 > MAXD) return hipErrorInvalidValue;
     int64_t gx = a.nbtot;
     if (gx > 65535) gx = 65535;
-    const dim3 grid((unsigned)gx, (unsigned)nsets), block(256);
-    switch (a.d0) {
-        case 2: hipLaunchKernelGGL(reduce_kernel<2>, grid, block, (size_t)lds_bytes, s, a); break;
-        case 3: hipLaunchKernelGGL(reduce_kernel<3>, grid, block, (size_t)lds_bytes, s, a); break;
-        case 4: hipLaunchKernelGGL(reduce_kernel<4>, grid, block, (size_t)lds_bytes, s, a); break;
-        case 5: hipLaunchKernelGGL(reduce_kernel<5>, grid, block, (size_t)lds_bytes, s, a); break;
-        case 6: hipLaunchKernelGGL(reduce_kernel<6>, grid, block, (size_t)lds_bytes, s, a); break;
-        case 7: hipLaunchKernelGGL(reduce_kernel<7>, grid, block, (size_t)lds_bytes, s, a); break;
-        case 8: hipLaunchKernelGGL(reduce_kernel<8>, grid, block, (size_t)lds_bytes, s, a); break;
-        case 9: hipLaunchKernelGGL(reduce_kernel<9>, grid, block, (size_t)lds_bytes, s, a); break;
-        case 10: hipLaunchKernelGGL(reduce_kernel<10>, grid, block, (size_t)lds_bytes, s, a); break;
-        default: return hipErrorInvalidValue;
-    }
+    const dim3 grid((unsigned)gx, (unsigned)nsets);
+    if (block_elems <= 64 * EPT)
+        launch_reduce_nt<64>(a, grid, lds_bytes, s);
+    else
+        launch_reduce_nt<256>(a, grid, lds_bytes, s);
     return hipGetLastError();
 }
 

@@ -72,7 +72,8 @@ int lds_bytes_moment(int prec, int n);
 hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xst, int prec,
                         bool center, bool in_f64, hipStream_t s);
 hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s);
-hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, hipStream_t s);
+// block_elems: b^d of the launch's first order (it picks the work-group size)
+hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, int block_elems, hipStream_t s);
 hipError_t launch_chunksum(const SetRed *sets, const SetRed &set0, int nsets, int64_t entries, hipStream_t s);
 hipError_t launch_axpy(double *y, const double *x, double a, int64_t count, hipStream_t s);
 hipError_t launch_stream_sum1(double *s1, const double *bmean, const double *shift, double tb, int n, hipStream_t s);
