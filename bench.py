@@ -270,16 +270,17 @@ def bench_workloads(torch, pc, orc, steps, tune):
     return out
 
 
-def bench_small(torch, pc, steps):
+def bench_small(torch, pc, steps, tune):
     """The launch-bound workload (n = 16, t = 5000, d <= 4, b = 2, FP64 path):
     per-call latency of eager calls and of replays of a HIP graph captured
-    from one call."""
+    from one call (autotuned like the other paths)."""
     import workloads
 
     name = "t-wishart-n16-t5000"
     w = workloads.WORKLOADS[name]
     n, b, d_max, t = w["n"], w["b"], w["d_max"], w["t"]
     Xd = torch.from_numpy(workloads.generate(name)).cuda()
+    tuned = pc.autotune(Xd, d_max, b, "f64") if tune else None
     out = {d: torch.empty(pc.layout(n, d, b)["elems"], dtype=torch.float64, device="cuda")
            for d in range(2, d_max + 1)}
     ws = torch.empty(pc.workspace_size(t, n, d_max, b, "f64"), dtype=torch.uint8, device="cuda")
@@ -310,7 +311,7 @@ def bench_small(torch, pc, steps):
     graph_us = e0.elapsed_time(e1) / steps * 1e3
     flops = alg_flops(pc, t, n, d_max, b)
     return {"workload": name, "prec": "f64", "eager_us_per_call": eager_us, "graph_us_per_replay": graph_us,
-            "eff_tflops_graph": flops / (graph_us * 1e-6) / 1e12}
+            "eff_tflops_graph": flops / (graph_us * 1e-6) / 1e12, "tuning": tuned}
 
 
 def traffic_record(prec, workload):
@@ -442,7 +443,7 @@ def main():
             f"{line['batched']['per_dataset_calls']['datasets_per_s']:.0f} with one call per dataset")
     if not args.no_workloads:
         line["workloads"] = bench_workloads(torch, pc, orc, max(5, args.steps // 2), not args.no_tune)
-        line["small"] = bench_small(torch, pc, max(50, args.steps * 5))
+        line["small"] = bench_small(torch, pc, max(50, args.steps * 5), not args.no_tune)
         log(f"  small workload: {line['small']['eager_us_per_call']:.1f} us per eager call, "
             f"{line['small']['graph_us_per_replay']:.1f} us per graph replay")
     if not args.no_cpu_baseline:
