@@ -224,7 +224,7 @@ struct OrderPlan {
     int32_t mstart[MAXD] = {0};   // first staged slot of each set size m (index m - 2)
     int lds_elems = 0;            // 0: the recursion reads lower orders from memory
     bool uploaded = false;
-    DevBuf rows_d, cols_d, rbv_d, cbw_d, H_d, prank_d, tuples_d, parts_d, smask_d, gmap_d;
+    DevBuf rows_d, cols_d, H_d, prank_d, tuples_d, parts_d, smask_d, gmap_d;
 };
 
 static cum_status build_order(int n, int b, int d, OrderPlan &o) {
@@ -382,8 +382,7 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
 static cum_status upload_order(OrderPlan &o) {
     if (o.uploaded) return CUM_OK;
     cum_status st;
-    if ((st = upload(o.rows_d, o.rows)) || (st = upload(o.cols_d, o.cols)) || (st = upload(o.rbv_d, o.rv16)) ||
-        (st = upload(o.cbw_d, o.cw16)) || (st = upload(o.H_d, o.H)) || (st = upload(o.prank_d, o.prank)) ||
+    if ((st = upload(o.rows_d, o.rows)) || (st = upload(o.cols_d, o.cols)) || (st = upload(o.H_d, o.H)) || (st = upload(o.prank_d, o.prank)) ||
         (st = upload(o.tuples_d, o.tuples)) ||
         (st = upload(o.parts_d, o.parts)) || (st = upload(o.smask_d, o.smask)) ||
         (st = upload(o.gmap_d, o.gmap)))
@@ -432,10 +431,12 @@ static void order_tiles(const OrderPlan &o, int wn, int ord_index, std::vector<H
             int mask = 0, cost = 0;
             for (int j = 0; j < wn && cb + j < ncb; ++j) {
                 if (o.rb_vmin[rb] > o.cb_wmax[cb + j]) continue;
-                mask |= 1 << j;
                 for (int h = 0; h < 2; ++h)
                     for (int g = 0; g < 2; ++g)
-                        if (o.rv16[2 * rb + h] <= o.cw16[2 * (cb + j) + g]) ++cost;
+                        if (o.rv16[2 * rb + h] <= o.cw16[2 * (cb + j) + g]) {
+                            mask |= 1 << (j * 4 + h * 2 + g);
+                            ++cost;
+                        }
             }
             if (mask) tasks.push_back({{rb * 32, cb * 32, mask, 0}, cost});
         }
@@ -460,8 +461,6 @@ static OrderDev order_dev(const OrderPlan &o, int64_t off) {
     OrderDev od;
     od.rows = (const Feat *)o.rows_d.p;
     od.cols = (const Feat *)o.cols_d.p;
-    od.rv16 = (const int32_t *)o.rbv_d.p;
-    od.cw16 = (const int32_t *)o.cbw_d.p;
     od.H = (const int64_t *)o.H_d.p;
     od.out_off = off;
     od.elems = o.elems;
@@ -1152,13 +1151,14 @@ cum_status cum_plan_check(int n, int d, int b) {
         for (const auto &ht : tiles)
             for (int w = 0; w < ht.t.ntask; ++w) {
                 const WaveTask &wt = ht.t.task[w];
+                if (wt.mask >> (4 * wn)) return fail(CUM_EINVAL, "d=%d: task mask 0x%x", d, wt.mask);
                 for (int j = 0; j < wn; ++j) {
-                    if (!(wt.mask >> j & 1)) continue;
                     for (int r = wt.r0; r < wt.r0 + 32; ++r)
                         for (int c = wt.c0 + 32 * j; c < std::min(o.nc, wt.c0 + 32 * j + 32); ++c) {
                             const Feat &fr = o.rows[r], &fc = o.cols[c];
                             const bool stored = fr.blk <= fc.blk;
-                            const bool computed = o.rv16[r / 16] <= o.cw16[c / 16];
+                            const int bit = j * 4 + (r - wt.r0) / 16 * 2 + (c - wt.c0 - 32 * j) / 16;
+                            const bool computed = wt.mask >> bit & 1;
                             if (stored && !computed)
                                 return fail(CUM_EINVAL, "d=%d: entry (%d,%d) lies in a skipped block", d, r, c);
                             if (!stored) continue;

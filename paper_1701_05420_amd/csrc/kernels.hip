@@ -308,24 +308,42 @@ __device__ __forceinline__ void stage_dma(const char *src, char *lds, int bytes,
 
 __device__ __forceinline__ void wait_dma() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
+// The BF16 split of eight FP32 values, two at a time: each pair is rounded
+// to nearest even by one packed conversion, and the residual of each term is
+// exact in FP32.
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ bf2 to_bf2(f2 x) { return __builtin_convertvector(x, bf2); }
+__device__ __forceinline__ f2 to_f2(bf2 x) { return __builtin_convertvector(x, f2); }
+
 __device__ __forceinline__ void split2(const float *v, bf8 &hi, bf8 &lo) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const __bf16 h = (__bf16)v[k];
-        hi[k] = h;
-        lo[k] = (__bf16)(v[k] - (float)h);
+    for (int k = 0; k < 8; k += 2) {
+        const f2 x = {v[k], v[k + 1]};
+        const bf2 h = to_bf2(x);
+        const bf2 l = to_bf2(x - to_f2(h));
+        hi[k] = h[0];
+        hi[k + 1] = h[1];
+        lo[k] = l[0];
+        lo[k + 1] = l[1];
     }
 }
 
 __device__ __forceinline__ void split3(const float *v, bf8 &hi, bf8 &mid, bf8 &lo) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const __bf16 h = (__bf16)v[k];
-        const float r = v[k] - (float)h;
-        const __bf16 m = (__bf16)r;
-        hi[k] = h;
-        mid[k] = m;
-        lo[k] = (__bf16)(r - (float)m);
+    for (int k = 0; k < 8; k += 2) {
+        const f2 x = {v[k], v[k + 1]};
+        const bf2 h = to_bf2(x);
+        const f2 r = x - to_f2(h);
+        const bf2 m = to_bf2(r);
+        const bf2 l = to_bf2(r - to_f2(m));
+        hi[k] = h[0];
+        hi[k + 1] = h[1];
+        mid[k] = m[0];
+        mid[k + 1] = m[1];
+        lo[k] = l[0];
+        lo[k + 1] = l[1];
     }
 }
 
@@ -349,22 +367,10 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
     const int soff = VEC * (lane >> 4);
 
     // which 16 x 16 sub-blocks of this wave's 32 x (32*WN) task hold stored
-    // entries (wave-uniform): bit (j*4 + h*2 + g)
-    unsigned vmask = 0;
-    if (active) {
-#pragma unroll
-        for (int j = 0; j < WN; ++j)
-            if (wt.mask >> j & 1)
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int g = 0; g < 2; ++g)
-                        if (od.rv16[(rbase >> 4) + h] <= od.cw16[((cbase + 32 * j) >> 4) + g])
-                            vmask |= 1u << (j * 4 + h * 2 + g);
-    }
-    // the mask is the same in every lane; say so, so that the per-sub-block
-    // tests below are scalar branches and not exec-mask regions
-    vmask = __builtin_amdgcn_readfirstlane(vmask);
+    // entries: bit (j*4 + h*2 + g).  The mask is the same in every lane; say
+    // so, so that the per-sub-block tests below are scalar branches and not
+    // exec-mask regions
+    const unsigned vmask = __builtin_amdgcn_readfirstlane(active ? (unsigned)wt.mask : 0u);
 
     // LDS offsets (in T) of this lane's operand variables, plus its sample offset
     int roff[2][P], coff[WN][2][Q];
@@ -409,8 +415,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
     const int nst = (int)(min(sd.nstages, st0 + sd.chunk_stages) - st0);
     const char *src = reinterpret_cast<const char *>(sd.X) + st0 * (int64_t)stage_bytes;
 
-    __syncthreads();  // the previous item's readers are done with both buffers
-    stage_dma(src, lds, stage_bytes, wave, lane);
+    // the first stage's copy was issued before the tile's records were read
     wait_dma();
     __syncthreads();
 
@@ -627,9 +632,17 @@ __global__ __launch_bounds__(64 * WG_WAVES, (moment_occupancy<PREC, WN, DMAX>())
     for (int64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
         const Item item = a.items[it];
         if (item.tile < 0) continue;
+        const SetDev sd = a.sets ? a.sets[item.set] : a.set0;
+        // Copy the chunk's first stage to LDS before reading the tile's
+        // records, so that the two latencies overlap.  No wave reads LDS
+        // after the last barrier of a previous item, so the buffer is free.
+        {
+            const int stage_bytes = (a.n + 1) * PT<PREC>::KTP * (int)sizeof(typename PT<PREC>::T);
+            stage_dma(reinterpret_cast<const char *>(sd.X) + (int64_t)item.chunk * sd.chunk_stages * stage_bytes, lds,
+                      stage_bytes, wave, threadIdx.x & 63);
+        }
         const TileDev *tile = a.tiles + item.tile;
         const OrderDev od = a.ords[tile->ord];
-        const SetDev sd = a.sets ? a.sets[item.set] : a.set0;
         switch (od.p * 8 + od.q) {
             case 1 * 8 + 1: moment_item<PREC, WN, 1, 1>(item, tile, od, sd, lds, a.n, wave); break;
             case 1 * 8 + 2: moment_item<PREC, WN, 1, 2>(item, tile, od, sd, lds, a.n, wave); break;

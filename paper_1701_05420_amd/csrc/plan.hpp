@@ -40,8 +40,6 @@ static_assert(sizeof(Feat) == 24, "Feat layout");
 struct OrderDev {
     const Feat *rows;
     const Feat *cols;
-    const int32_t *rv16;     // per 16-row block: smallest v of its real rows
-    const int32_t *cw16;     // per 16-col block: largest w of its real columns
     const int64_t *H;        // nbar x nbar: (v, w) term of the rank, times b^d
     int64_t out_off;         // offset of this order in the per-chunk partial vector
     int64_t elems;           // stored entries of this order
@@ -49,7 +47,9 @@ struct OrderDev {
 };
 
 // One wave's share of a work item: rows r0..r0+31 by WN column blocks of 32
-// starting at c0; bit j of mask: column block j holds a stored entry.
+// starting at c0.  Bit j*4 + h*2 + g of mask: the 16 x 16 sub-block of rows
+// r0+16h.. and columns c0+32j+16g.. holds a stored entry (the others are
+// skipped).
 struct WaveTask {
     int32_t r0;
     int32_t c0;
