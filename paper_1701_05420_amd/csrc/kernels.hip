@@ -564,7 +564,13 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
         wait_dma();
         __syncthreads();
         if constexpr (PREC != P_F64) {
-            // FP32 sums cover one stage; carry them in FP64
+            // The FP32 sums of the leading products cover one stage and are
+            // carried in FP64.  The three-term path's small products (2^-8 of
+            // the leading ones and smaller) are carried over up to four stages
+            // first: their FP32 rounding stays far below that of the leading
+            // sums, and the conversions they save are a sizeable part of the
+            // path's vector work.
+            const bool small = PREC == P_BF16X3 && ((k & 3) == 3 || k + 1 == nst);
 #pragma unroll
             for (int j = 0; j < WN; ++j)
 #pragma unroll
@@ -573,14 +579,22 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                     for (int g = 0; g < 2; ++g)
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            if constexpr (PREC == P_BF16X3) {
-                                dacc[j][h][g][q] += (double)acc[j][h][g][q] + (double)acc2[j][h][g][q];
-                                acc2[j][h][g][q] = 0.f;
-                            } else {
-                                dacc[j][h][g][q] += (double)acc[j][h][g][q];
-                            }
+                            dacc[j][h][g][q] += (double)acc[j][h][g][q];
                             acc[j][h][g][q] = 0.f;
                         }
+            if (small) {
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int g = 0; g < 2; ++g)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                dacc[j][h][g][q] += (double)acc2[j][h][g][q];
+                                acc2[j][h][g][q] = 0.f;
+                            }
+            }
         }
     }
 
