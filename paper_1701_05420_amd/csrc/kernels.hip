@@ -662,24 +662,46 @@ __global__ __launch_bounds__(64 * WG_WAVES, (moment_occupancy<PREC, WN, DMAX>())
             case 1 * 8 + 2: moment_item<PREC, WN, 1, 2>(item, tile, od, sd, lds, a.n, wave); break;
             case 2 * 8 + 2: moment_item<PREC, WN, 2, 2>(item, tile, od, sd, lds, a.n, wave); break;
             case 2 * 8 + 3:
-                if constexpr (DMAX >= 5) moment_item<PREC, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave);
+                if constexpr (DMAX >= 5)
+                    moment_item<PREC, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave);
+                else
+                    wait_dma();
                 break;
             case 3 * 8 + 3:
-                if constexpr (DMAX >= 6) moment_item<PREC, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave);
+                if constexpr (DMAX >= 6)
+                    moment_item<PREC, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave);
+                else
+                    wait_dma();
                 break;
             case 3 * 8 + 4:
-                if constexpr (DMAX >= 7) moment_item<PREC, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave);
+                if constexpr (DMAX >= 7)
+                    moment_item<PREC, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave);
+                else
+                    wait_dma();
                 break;
             case 4 * 8 + 4:
-                if constexpr (DMAX >= 8) moment_item<PREC, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave);
+                if constexpr (DMAX >= 8)
+                    moment_item<PREC, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave);
+                else
+                    wait_dma();
                 break;
             case 4 * 8 + 5:
-                if constexpr (DMAX >= 9) moment_item<PREC, WN, 4, 5>(item, tile, od, sd, lds, a.n, wave);
+                if constexpr (DMAX >= 9)
+                    moment_item<PREC, WN, 4, 5>(item, tile, od, sd, lds, a.n, wave);
+                else
+                    wait_dma();
                 break;
             case 5 * 8 + 5:
-                if constexpr (DMAX >= 10) moment_item<PREC, WN, 5, 5>(item, tile, od, sd, lds, a.n, wave);
+                if constexpr (DMAX >= 10)
+                    moment_item<PREC, WN, 5, 5>(item, tile, od, sd, lds, a.n, wave);
+                else
+                    wait_dma();
                 break;
-            default: break;
+            default:
+                // not a split of this launch's orders (the plans never ask for
+                // one): let the first stage's copy land before the wave ends
+                wait_dma();
+                break;
         }
     }
 }
