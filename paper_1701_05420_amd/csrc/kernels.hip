@@ -313,6 +313,7 @@ __device__ __forceinline__ void wait_dma() { __builtin_amdgcn_s_waitcnt(0x0F70);
 // exact in FP32.
 typedef float f2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ bf2 to_bf2(f2 x) { return __builtin_convertvector(x, bf2); }
 __device__ __forceinline__ f2 to_f2(bf2 x) { return __builtin_convertvector(x, f2); }
@@ -330,14 +331,30 @@ __device__ __forceinline__ void split2(const float *v, bf8 &hi, bf8 &lo) {
     }
 }
 
+// Two FP32 values whose low 16 bits are zero (exact in BF16), packed by
+// moving bits: no conversion instruction.
+__device__ __forceinline__ bf2 pack_exact(f2 x) {
+    // (the whole vector is cast: a cast of one element reads element 0)
+    const u2 u = __builtin_bit_cast(u2, x);
+    return __builtin_bit_cast(bf2, (u[0] >> 16) | (u[1] & 0xffff0000u));
+}
+
+// The third term: x - hi is a multiple of x's FP32 ulp no larger than half a
+// BF16 ulp of x, so it holds at most 16 significant bits; less its own
+// rounding to BF16 (mid) at most 8 remain, and the FP32 value is exact in
+// BF16 (below the FP32 normal range, packing truncates where a conversion
+// would round, a difference under 2^-133).  This needs x to be the FP32
+// value of the product: contraction is off here, so that x - hi is not
+// fused with the multiplication into a residual of the exact product.
 __device__ __forceinline__ void split3(const float *v, bf8 &hi, bf8 &mid, bf8 &lo) {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int k = 0; k < 8; k += 2) {
         const f2 x = {v[k], v[k + 1]};
         const bf2 h = to_bf2(x);
         const f2 r = x - to_f2(h);
         const bf2 m = to_bf2(r);
-        const bf2 l = to_bf2(r - to_f2(m));
+        const bf2 l = pack_exact(r - to_f2(m));
         hi[k] = h[0];
         hi[k + 1] = h[1];
         mid[k] = m[0];
