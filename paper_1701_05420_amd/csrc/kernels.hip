@@ -581,25 +581,28 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
         wait_dma();
         __syncthreads();
         if constexpr (PREC != P_F64) {
-            // The FP32 sums of the leading products cover one stage and are
-            // carried in FP64.  The three-term path's small products (2^-8 of
-            // the leading ones and smaller) are carried over up to four stages
-            // first: their FP32 rounding stays far below that of the leading
-            // sums, and the conversions they save are a sizeable part of the
-            // path's vector work.
-            const bool small = PREC == P_BF16X3 && ((k & 3) == 3 || k + 1 == nst);
+            // Carry the FP32 sums into FP64.  The leading products of the FP32
+            // and three-term paths are carried after every stage.  The
+            // three-term path's small products (2^-8 of the leading ones and
+            // smaller) and the two-term path's sums, whose error is set by its
+            // 16-bit operands, are carried every fourth stage: their FP32
+            // roundings stay far below the path's own error, and the
+            // conversions saved are a sizeable part of the vector work.
+            const bool fourth = (k & 3) == 3 || k + 1 == nst;
+            if (PREC != P_BF16X2 || fourth) {
 #pragma unroll
-            for (int j = 0; j < WN; ++j)
+                for (int j = 0; j < WN; ++j)
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
+                    for (int h = 0; h < 2; ++h)
 #pragma unroll
-                    for (int g = 0; g < 2; ++g)
+                        for (int g = 0; g < 2; ++g)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            dacc[j][h][g][q] += (double)acc[j][h][g][q];
-                            acc[j][h][g][q] = 0.f;
-                        }
-            if (small) {
+                            for (int q = 0; q < 4; ++q) {
+                                dacc[j][h][g][q] += (double)acc[j][h][g][q];
+                                acc[j][h][g][q] = 0.f;
+                            }
+            }
+            if (PREC == P_BF16X3 && fourth) {
 #pragma unroll
                 for (int j = 0; j < WN; ++j)
 #pragma unroll
