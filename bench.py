@@ -314,9 +314,10 @@ def bench_small(torch, pc, steps, tune):
             "eff_tflops_graph": flops / (graph_us * 1e-6) / 1e12, "tuning": tuned}
 
 
-def traffic_record(prec, workload):
-    """HBM bytes per moment launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+def profile_record(prec, workload):
+    """The committed rocprofv3 counter summary of the moment kernel (HBM bytes
+    and matrix-unit use per launch), if it was taken on the current kernel
+    source; else None."""
     path = os.path.join(ROOT, "profiles", f"moment_kernel_{prec}_{workload}.pmc.json")
     if not os.path.exists(path):
         return None
@@ -325,7 +326,7 @@ def traffic_record(prec, workload):
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if rec.get("kernels_hip_sha256") != sha:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
 
 
 def main():
@@ -411,9 +412,15 @@ def main():
     errs = {} if args.no_errors else sampled_errors(orc, pc, X, kappa, n, d_max, b)
     main_p = args.prec
     r = res[main_p]
+    prof = profile_record(main_p, args.workload)
+    prof_alg = r["moment_flop_per_launch"] * PRODUCTS[main_p]
     roof = {"bound": "mfma", "achieved": r["moment_tflops"] * PRODUCTS[main_p], "peak": PEAK[main_p],
             "unit": "TFLOP/s", "frac": r["moment_tflops"] * PRODUCTS[main_p] / PEAK[main_p],
-            "traffic": traffic_record(main_p, args.workload),
+            "traffic": prof.get("hbm_bytes_per_launch") if prof else None,
+            "mfma_util_pmc": ({"issued_frac_of_peak": prof["mfma_issued_frac_of_peak"],
+                               "busy_frac": prof["mfma_busy_frac"],
+                               "issued_over_algorithmic": prof["mfma_issued_flop_per_launch"] / prof_alg}
+                              if prof and "mfma_busy_frac" in prof else None),
             "kernel": "moment_kernel", "algorithmic_tflops": r["moment_tflops"],
             "flop_per_launch": r["moment_flop_per_launch"], "inner_b": r["config"]["inner_b"],
             "ms_per_launch": r["moment_ms_per_launch"]}
