@@ -196,3 +196,17 @@ def test_plan_info_counts(pc):
     info4 = pc.plan_info(*shape)
     assert info4["partial_entries"] == info4["stored_entries"]
     pc.set_tuning(*shape, None)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """A copy of the package without its built library refuses to import:
+    there is no fallback implementation to take over."""
+    import shutil
+
+    pkg = tmp_path / "paper_1701_05420_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_1701_05420_amd", "__init__.py"), pkg / "__init__.py")
+    out = subprocess.run([sys.executable, "-c", "import paper_1701_05420_amd"], cwd=tmp_path,
+                         env=dict(os.environ, PYTHONPATH=str(tmp_path)), capture_output=True, text=True, timeout=120)
+    assert out.returncode != 0
+    assert "ImportError" in out.stderr and "no fallback" in out.stderr
