@@ -262,8 +262,9 @@ hipError_t launch_batch_stamp(unsigned long long *stamps, int nsets, hipStream_t
 // 16-byte LDS read.  The sample order inside a stage is a free choice of the
 // sum, so lane group g of an MFMA takes samples g*VEC .. g*VEC+VEC-1 of each
 // group of steps.  16 x 16 sub-blocks with no stored entry (v > w everywhere)
-// are skipped per wave.  The chunk's sums go, in FP64, to the chunk's slice of
-// the partial buffer at each entry's block-storage offset.
+// are skipped per wave, as the task's mask (built on the host) says.  The
+// chunk's sums go, in FP64, to the chunk's slice of the partial buffer, at
+// each entry's offset in the block storage of the inner block size.
 // ---------------------------------------------------------------------------
 template <int PREC>
 struct PT;
@@ -308,9 +309,8 @@ __device__ __forceinline__ void stage_dma(const char *src, char *lds, int bytes,
 
 __device__ __forceinline__ void wait_dma() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
-// The BF16 split of eight FP32 values, two at a time: each pair is rounded
-// to nearest even by one packed conversion, and the residual of each term is
-// exact in FP32.
+// The BF16 splits of eight FP32 values, two at a time: each rounding to
+// nearest even converts a pair with one packed conversion.
 typedef float f2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 typedef unsigned u2 __attribute__((ext_vector_type(2)));
@@ -318,6 +318,8 @@ typedef unsigned u2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ bf2 to_bf2(f2 x) { return __builtin_convertvector(x, bf2); }
 __device__ __forceinline__ f2 to_f2(bf2 x) { return __builtin_convertvector(x, f2); }
 
+// Two terms: hi, and lo = x - hi rounded (the compiler may form x - hi from
+// the unrounded product with one fused multiply-add, which only helps lo).
 __device__ __forceinline__ void split2(const float *v, bf8 &hi, bf8 &lo) {
 #pragma unroll
     for (int k = 0; k < 8; k += 2) {
