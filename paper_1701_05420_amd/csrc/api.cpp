@@ -227,6 +227,51 @@ struct OrderPlan {
     DevBuf rows_d, cols_d, H_d, prank_d, tuples_d, parts_d, smask_d, gmap_d;
 };
 
+// Cut points of the sorted rows (or columns) into 16-blocks.  A 16 x 16
+// sub-block is computed when the smallest v of its rows is <= the largest w
+// of its columns, so each row block costs as many sub-blocks as there are
+// column blocks with w_max >= its smallest v, whatever number of real rows it
+// holds; likewise for column blocks.  Given the other side's blocks, a
+// dynamic program over the cut points (blocks of 1 to 16 consecutive
+// features, the rest padding) minimises the computed sub-blocks.  cost[k] is
+// the cost of a block whose key (the first feature's block index for rows,
+// the last one's for columns) is k.  Returns the block sizes in order.
+static std::vector<int> align_blocks(const std::vector<Feat> &f, const std::vector<int64_t> &cost, bool key_first) {
+    const size_t N = f.size();
+    std::vector<int64_t> best(N + 1, 0);
+    std::vector<int> take(N + 1, 0);
+    for (size_t i = 1; i <= N; ++i) {
+        best[i] = INT64_MAX;
+        for (int sz = 1; sz <= 16 && (size_t)sz <= i; ++sz) {
+            const int key = key_first ? f[i - sz].blk : f[i - 1].blk;
+            const int64_t c = best[i - sz] + cost[key];
+            if (c < best[i]) {
+                best[i] = c;
+                take[i] = sz;
+            }
+        }
+    }
+    std::vector<int> sizes;
+    for (size_t i = N; i > 0; i -= take[i]) sizes.push_back(take[i]);
+    std::reverse(sizes.begin(), sizes.end());
+    return sizes;
+}
+
+// Rows and columns laid out in 16-blocks of the given sizes, padded.
+static std::vector<Feat> pad_blocks(const std::vector<Feat> &f, const std::vector<int> &sizes, const Feat &pad) {
+    std::vector<Feat> out;
+    out.reserve(sizes.size() * 16);
+    size_t i = 0;
+    for (int sz : sizes) {
+        for (int k = 0; k < sz; ++k) out.push_back(f[i++]);
+        for (int k = sz; k < 16; ++k) out.push_back(pad);
+    }
+    return out;
+}
+
+// Plain packing (full 16-blocks) when the dynamic program would take too long.
+constexpr size_t ALIGN_MAX_FEATURES = 1 << 22;
+
 static cum_status build_order(int n, int b, int d, OrderPlan &o) {
     o.n = n;
     o.b = b;
@@ -296,9 +341,6 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
             o.cols.push_back(f);
         }
     }
-    const int nr_real = (int)o.rows.size(), nc_real = (int)o.cols.size();
-    o.nr = (nr_real + FEAT_BLOCK - 1) / FEAT_BLOCK * FEAT_BLOCK;
-    o.nc = (nc_real + FEAT_BLOCK - 1) / FEAT_BLOCK * FEAT_BLOCK;
     // padding rows and columns multiply the zero row only
     Feat padr, padc;
     memset(&padr, 0, sizeof padr);
@@ -306,6 +348,40 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
     for (int k = 0; k < MAXH; ++k) padr.var[k] = (uint8_t)n;
     padc = padr;
     padc.blk = -1;
+    // 16-blocks cut where they waste the fewest matrix products on unstored
+    // entries (alternating between rows and columns, each pass optimal given
+    // the other side; a pass never increases the count)
+    if (o.rows.size() <= ALIGN_MAX_FEATURES && o.cols.size() <= ALIGN_MAX_FEATURES) {
+        std::vector<int> rsz((o.rows.size() + 15) / 16, 16), csz((o.cols.size() + 15) / 16, 16);
+        if (!rsz.empty()) rsz.back() = (int)(o.rows.size() - 16 * (rsz.size() - 1));
+        if (!csz.empty()) csz.back() = (int)(o.cols.size() - 16 * (csz.size() - 1));
+        auto keys = [](const std::vector<Feat> &f, const std::vector<int> &sz, bool first) {
+            std::vector<int> k;
+            size_t i = 0;
+            for (int z : sz) {
+                k.push_back(first ? f[i].blk : f[i + z - 1].blk);
+                i += z;
+            }
+            return k;
+        };
+        for (int pass = 0; pass < 3; ++pass) {
+            // rows: a block with smallest v costs the column blocks with w_max >= v
+            std::vector<int64_t> cost(nbar + 1, 0);
+            for (int w : keys(o.cols, csz, false)) ++cost[w];
+            for (int v = nbar - 1; v >= 0; --v) cost[v] += cost[v + 1];
+            rsz = align_blocks(o.rows, cost, true);
+            // columns: a block with largest w costs the row blocks with v_min <= w
+            std::vector<int64_t> cc(nbar, 0);
+            for (int v : keys(o.rows, rsz, true)) ++cc[v];
+            for (int w = 1; w < nbar; ++w) cc[w] += cc[w - 1];
+            csz = align_blocks(o.cols, cc, false);
+        }
+        o.rows = pad_blocks(o.rows, rsz, padr);
+        o.cols = pad_blocks(o.cols, csz, padc);
+    }
+    const int nr_real = (int)o.rows.size(), nc_real = (int)o.cols.size();
+    o.nr = (nr_real + FEAT_BLOCK - 1) / FEAT_BLOCK * FEAT_BLOCK;
+    o.nc = (nc_real + FEAT_BLOCK - 1) / FEAT_BLOCK * FEAT_BLOCK;
     o.rows.resize(o.nr, padr);
     o.cols.resize(o.nc, padc);
     for (int rb = 0; rb < o.nr / FEAT_BLOCK; ++rb) {
