@@ -52,3 +52,29 @@ def test_high_order_float_fp64(dev, orc):
         e = np.abs(K[d].cpu().numpy() - want).max() / np.abs(want).max()
         say(f"  e_{d} = {e:.3e}")
         assert e <= 1e-10, (d, e)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3"])
+@pytest.mark.parametrize("n,b,dmax", [(6, 4, 9), (5, 2, 10)])
+def test_high_order_float_sampled(dev, orc, prec, n, b, dmax):
+    """Orders 9 and 10 on float data, every precision: the oracle's per-entry
+    route (all set partitions of the positions, FP64) at 64 random multi-
+    indices and every pure diagonal, read through the block storage.  The
+    error is taken relative to max(max|oracle|, s_d), s_d = max_i mean_l
+    |x~_li|^d, which bounds every entry of M_d."""
+    torch, pc = dev
+    TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
+    X = workloads.laplace_mix(t=2000, n=n, seed=90 + n)
+    say(f"high order sampled prec={prec} n={n} b={b} dmax={dmax}")
+    mean, K = pc.cumulants(torch.from_numpy(X).cuda(), dmax, b, prec)
+    torch.cuda.synchronize()
+    Xc = X - X.mean(axis=0)
+    rng = np.random.default_rng(n * 100 + dmax)
+    for d in (dmax - 1, dmax):
+        idx = np.concatenate([rng.integers(0, n, size=(64, d)), np.repeat(np.arange(n)[:, None], d, axis=1)])
+        want = orc.cumulant_at(Xc, idx.astype(np.int32))
+        got = K[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
+        s_d = (np.abs(Xc) ** d).mean(axis=0).max()
+        e = np.abs(got - want).max() / max(np.abs(want).max(), s_d)
+        say(f"  e_{d} = {e:.3e}")
+        assert e <= TOL[prec], (d, e)
