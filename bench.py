@@ -314,6 +314,65 @@ def bench_small(torch, pc, steps, tune):
             "eff_tflops_graph": flops / (graph_us * 1e-6) / 1e12, "tuning": tuned}
 
 
+def bench_streaming(torch, pc, X, n, d_max, b, prec, steps, batch=10_000, window=5):
+    """A rolling window over the benchmark data: `window` batches of `batch`
+    samples; one slide adds the next batch and removes the oldest (two
+    updates).  Reports the slide time, the update rate (samples and FLOP: the
+    contraction of each update sums every sorted variable tuple of orders
+    2..d_max once), the latency of the window's cumulants by the recursion and
+    by the general formula, and both against one FP64 call on the window's
+    samples."""
+    t = X.shape[0]
+    nb = t // batch
+    Xd = torch.from_numpy(X).cuda()
+    batches = [Xd[i * batch:(i + 1) * batch] for i in range(nb)]
+    st = pc.Stream(n, d_max, b, prec)
+    try:
+        for i in range(window):
+            st.add(batches[i])
+        first = 0
+
+        def slide(k):
+            st.add(batches[(first + window + k) % nb])
+            st.remove(batches[(first + k) % nb])
+
+        for k in range(2):
+            slide(k)
+        first += 2
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(steps):
+            slide(k)
+        e1.record()
+        torch.cuda.synchronize()
+        first += steps
+        slide_ms = e0.elapsed_time(e1) / steps
+        lat, res = {}, {}
+        for method in ("recursion", "moebius"):
+            st.cumulants(method=method)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(5):
+                mean, K = st.cumulants(method=method)
+            e1.record()
+            torch.cuda.synchronize()
+            lat[method] = e0.elapsed_time(e1) / 5
+            res[method] = {d: K[d].cpu().numpy() for d in K}
+        win = torch.cat([batches[(first + i) % nb] for i in range(window)])
+        _, R = pc.cumulants(win, d_max, b, "f64")
+        ref = {d: R[d].cpu().numpy() for d in R}
+    finally:
+        st.close()
+    diff = {m: {str(d): float(np.abs(res[m][d] - ref[d]).max() / np.abs(ref[d]).max()) for d in ref} for m in res}
+    uflop = 2.0 * batch * sum(math.comb(n + d - 1, d) for d in range(2, d_max + 1))
+    return {"workload": f"rolling window of {window} x {batch} samples over the benchmark data", "prec": prec,
+            "batch": batch, "window_batches": window, "ms_per_slide": slide_ms,
+            "samples_per_s": 2 * batch / (slide_ms * 1e-3),
+            "update_tflops": 2 * uflop / (slide_ms * 1e-3) / 1e12,
+            "cumulants_ms": lat, "rel_diff_vs_one_call_f64": diff}
+
+
 def profile_record(prec, workload):
     """The committed rocprofv3 counter summary of the moment kernel (HBM bytes
     and matrix-unit use per launch), if it was taken on the current kernel
@@ -343,6 +402,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (planner defaults)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-dataset batched measurement")
     ap.add_argument("--no-workloads", action="store_true", help="skip the d_max = 5, 6 workloads")
+    ap.add_argument("--no-streaming", action="store_true", help="skip the rolling-window measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -448,6 +508,13 @@ def main():
         line["batched"] = bench_batched(torch, pc, main_p, max(3, args.steps // 4), 1, not args.no_tune)
         log(f"  batched: {line['batched']['datasets_per_s']:.0f} datasets/s vs "
             f"{line['batched']['per_dataset_calls']['datasets_per_s']:.0f} with one call per dataset")
+    if not args.no_streaming:
+        log("streaming window")
+        sw = bench_streaming(torch, pc, X, n, d_max, b, main_p, max(5, args.steps // 2))
+        line["streaming"] = sw
+        log(f"  slide of 2 x {sw['batch']} samples: {sw['ms_per_slide']:.3f} ms ({sw['samples_per_s'] / 1e6:.1f} M samples/s, "
+            f"{sw['update_tflops']:.1f} TFLOP/s); cumulants {sw['cumulants_ms']['recursion']:.3f} ms (recursion), "
+            f"{sw['cumulants_ms']['moebius']:.3f} ms (general formula)")
     if not args.no_workloads:
         line["workloads"] = bench_workloads(torch, pc, orc, max(5, args.steps // 2), not args.no_tune)
         line["small"] = bench_small(torch, pc, max(50, args.steps * 5), not args.no_tune)

@@ -729,7 +729,7 @@ static ItemSet *plan_items(CallPlan &c, int64_t nck) {
 }
 
 static cum_status get_call_cfg(int n, int b, int bi, int dlo, int dhi, int prec, int shape, int target, int64_t t,
-                               Call *out) {
+                               Call *out, int min_stages = 4) {
     auto key = std::make_tuple(n, b, bi, dlo, dhi, prec, shape, target);
     auto it = g_calls.find(key);
     CallPlan *c;
@@ -773,13 +773,13 @@ static cum_status get_call_cfg(int n, int b, int bi, int dlo, int dhi, int prec,
         g_calls[key] = std::move(cp);
     }
     // sample chunks (whole stages): about `target` work items (1024 fill the
-    // 256 CUs' four work-group slots once), chunks of >= 4 stages
+    // 256 CUs' four work-group slots once), chunks of >= min_stages stages
     Call k;
     k.c = c;
     k.t = t;
     k.nstages = (t + stage_kt(prec) - 1) / stage_kt(prec);
     const int64_t want = (target + std::max<int64_t>(c->ntiles, 1) - 1) / std::max<int64_t>(c->ntiles, 1);
-    const int64_t maxch = std::max<int64_t>(1, k.nstages / 4);
+    const int64_t maxch = std::max<int64_t>(1, k.nstages / min_stages);
     int64_t nch = std::max<int64_t>(1, std::min(want, maxch));
     if (nch >= 8) nch = (nch + 7) / 8 * 8;
     k.chunk_stages = (k.nstages + nch - 1) / nch;
@@ -1912,10 +1912,20 @@ cum_status cum_stream_update(cum_stream *p, const double *X, int64_t t, int64_t 
     std::lock_guard<std::mutex> lk(g_mu);
     hipStream_t s = (hipStream_t)stream;
     const int n = p->n;
-    // the contraction fills the layout of block size 1 (each sorted tuple once)
+    // the contraction fills the layout of block size 1 (each sorted tuple
+    // once); a tuned task shape and item target for this sample count apply.
+    // Untuned, chunks hold at least 16 stages: stream batches are often
+    // small, and short work items spend much of their time on set-up
     Call k;
-    if ((st = get_call_cfg(n, p->b, 1, 2, p->d_max, p->prec, default_shape(p->prec), DEFAULT_TARGET, t, &k)))
-        return st;
+    int shape = default_shape(p->prec), target = DEFAULT_TARGET, min_stages = 16;
+    load_tune_file();
+    auto tu = g_tuned.find(std::make_tuple(n, p->b, 2, p->d_max, p->prec, t));
+    if (tu != g_tuned.end()) {
+        shape = tu->second.shape;
+        target = tu->second.target;
+        min_stages = 4;
+    }
+    if ((st = get_call_cfg(n, p->b, 1, 2, p->d_max, p->prec, shape, target, t, &k, min_stages))) return st;
     if ((st = upload_call(k))) return st;
     int groups;
     int64_t rows_per;
