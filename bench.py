@@ -270,6 +270,39 @@ def bench_workloads(torch, pc, orc, steps, tune):
     return out
 
 
+def bench_high_orders(torch, pc, orc, steps):
+    """Orders to 8 and 10 (the recursion's partition tables grow to 715 and
+    17722 terms per entry): step time, effective throughput, the split of
+    kernel time between the contraction and the finalisation, and e_d of the
+    top orders against the oracle's per-entry route (FP32 path, planner
+    defaults)."""
+    import workloads
+
+    out = {}
+    for n, b, d_max, t in [(16, 2, 8, 20_000), (8, 2, 10, 20_000)]:
+        name = f"laplace-mix-n{n}-t{t}-d{d_max}"
+        log(f"high orders {name}")
+        X = workloads.laplace_mix(t=t, n=n, seed=1701006)
+        Xd = torch.from_numpy(X).cuda()
+        flops = alg_flops(pc, t, n, d_max, b)
+        wall, kinds, o, _, pct = time_path(torch, pc, Xd, d_max, b, "f32", steps, 2, False)
+        ms = {k: v[0] / steps for k, v in kinds.items() if v[1]}
+        Xc = X - X.mean(axis=0)
+        rng = np.random.default_rng(d_max)
+        errs = {}
+        for d in (d_max - 1, d_max):
+            idx = np.concatenate([rng.integers(0, n, size=(64, d)), np.repeat(np.arange(n)[:, None], d, axis=1)])
+            want = orc.cumulant_at(Xc, idx.astype(np.int32))
+            got = o[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
+            errs[str(d)] = float(np.abs(got - want).max() / np.abs(want).max())
+        out[name] = {"n": n, "b": b, "d_max": d_max, "t": t, "prec": "f32", "ms_per_step": wall * 1e3,
+                     "ms_per_step_pct": pct, "tflops": flops / wall / 1e12, "kernel_ms": ms,
+                     "stored_entries": pc.plan_info(t, n, d_max, b, "f32")["stored_entries"],
+                     "rel_err_sampled": errs}
+        log(f"  {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s; kernels {ms}; e {errs}")
+    return out
+
+
 def bench_small(torch, pc, steps, tune):
     """The launch-bound workload (n = 16, t = 5000, d <= 4, b = 2, FP64 path):
     per-call latency of eager calls and of replays of a HIP graph captured
@@ -518,6 +551,7 @@ def main():
     if not args.no_workloads:
         line["workloads"] = bench_workloads(torch, pc, orc, max(5, args.steps // 2), not args.no_tune)
         line["small"] = bench_small(torch, pc, max(50, args.steps * 5), not args.no_tune)
+        line["high_orders"] = bench_high_orders(torch, pc, orc, max(5, args.steps // 2))
         log(f"  small workload: {line['small']['eager_us_per_call']:.1f} us per eager call, "
             f"{line['small']['graph_us_per_replay']:.1f} us per graph replay")
     if not args.no_cpu_baseline:

@@ -219,12 +219,14 @@ struct OrderPlan {
     std::vector<uint8_t> tuples;
     std::vector<int32_t> parts;   // npart x (d/2), packed mask | where << 10
     int npart = 0;
+    std::vector<int32_t> terms;   // orders >= 7: nterm x 2 (set A with position 0, its complement)
+    int nterm = 0;
     std::vector<uint16_t> smask;  // position sets of 2..d-2 positions, by size then value
     std::vector<int32_t> gmap;    // staged slot -> s | flat << 10
     int32_t mstart[MAXD] = {0};   // first staged slot of each set size m (index m - 2)
     int lds_elems = 0;            // 0: the recursion reads lower orders from memory
     bool uploaded = false;
-    DevBuf rows_d, cols_d, H_d, prank_d, tuples_d, parts_d, smask_d, gmap_d;
+    DevBuf rows_d, cols_d, H_d, prank_d, tuples_d, parts_d, smask_d, gmap_d, terms_d;
 };
 
 // Cut points of the sorted rows (or columns) into 16-blocks.  A 16 x 16
@@ -451,6 +453,25 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
             }
             o.parts.push_back(v);
         }
+    // Orders >= 7 can also use the moment-cumulant relation split at the first
+    // position: the sum over partitions equals the sum over sets A holding
+    // position 0 (2 <= |A| <= d-2) of kappa_|A|(j_A) times the central moment
+    // M_(d-|A|) of the complement (sets of one position drop out: kappa_1 = 0
+    // and central M_1 = 0).  2^(d-1) - d - 1 terms of two factors, against
+    // 162, 715, 3425 and 17722 partitions at d = 7..10.
+    if (d >= FIRST_POSITION_MIN_D) {
+        const int full = (1 << d) - 1;
+        for (int mask = 1; mask < (1 << d); mask += 2) {
+            const int m = __builtin_popcount(mask);
+            if (m < 2 || m > d - 2) continue;
+            const int comp = full ^ mask;
+            for (int f : {mask, comp}) {
+                const int where = o.lds_elems ? (int)soff[(size_t)sidx[f]] : sidx[f];
+                o.terms.push_back((int32_t)f | (int32_t)(where << 10));
+            }
+        }
+        o.nterm = (int)o.terms.size() / 2;
+    }
 
     return CUM_OK;
 }
@@ -461,7 +482,7 @@ static cum_status upload_order(OrderPlan &o) {
     if ((st = upload(o.rows_d, o.rows)) || (st = upload(o.cols_d, o.cols)) || (st = upload(o.H_d, o.H)) || (st = upload(o.prank_d, o.prank)) ||
         (st = upload(o.tuples_d, o.tuples)) ||
         (st = upload(o.parts_d, o.parts)) || (st = upload(o.smask_d, o.smask)) ||
-        (st = upload(o.gmap_d, o.gmap)))
+        (st = upload(o.gmap_d, o.gmap)) || (st = upload(o.terms_d, o.terms)))
         return st;
     o.uploaded = true;
     return CUM_OK;
@@ -560,6 +581,8 @@ static RedOrder red_order(const OrderPlan &o, const OrderPlan &po, int64_t poff)
     ro.parts = (const int32_t *)o.parts_d.p;
     ro.smask = (const uint16_t *)o.smask_d.p;
     ro.gmap = (const int32_t *)o.gmap_d.p;
+    ro.terms = (const int32_t *)o.terms_d.p;
+    ro.nterm = o.nterm;
     ro.prank = (const int64_t *)po.prank_d.p;
     ro.ns = (int32_t)o.smask.size();
     ro.lds_elems = o.lds_elems;
@@ -834,12 +857,12 @@ static int red_lds_layout(const RedOrder *ro, int nords, bool recursion, RedArgs
         for (int i = 0; i < nords; ++i) {
             sub = std::max<int64_t>(sub, ro[i].lds_elems);
             ns = std::max<int64_t>(ns, ro[i].ns);
-            parts = std::max<int64_t>(parts, (int64_t)ro[i].npart * (ro[i].d / 2));
+            const bool fp = ra.subset && ro[i].d >= FIRST_POSITION_MIN_D && ro[i].nterm > 0;
+            parts = std::max<int64_t>(parts, fp ? (int64_t)ro[i].nterm * 2 : (int64_t)ro[i].npart * (ro[i].d / 2));
         }
     ra.base_off = (int32_t)((sub * 8 + 15) / 16 * 16);
     ra.parts_off = ra.base_off + (int32_t)((ns * 8 + 15) / 16 * 16);
     ra.parts_lds = (parts > 0 && ra.parts_off + parts * 4 <= 65536) ? 1 : 0;
-    ra.pad = 0;
     return ra.parts_off + (ra.parts_lds ? (int)(parts * 4) : 0);
 }
 
@@ -888,8 +911,11 @@ static cum_status run_contraction(const Call &k, const void *Xc, double *partial
 // Finalisation of orders dlo..dhi from moment sums S (nchunks chunks in the
 // call's partial-sum layout, added in chunk order): M = S / t and, with
 // recursion, the cumulants, into outs (block storage of block size b).
+// moms (or null): buffers in block storage for the central moments of
+// orders 2..dhi-2 (moms[m-2]); with them, orders >= 7 use the first-position
+// formula.
 static cum_status run_finalize(CallPlan *c, double *sums, int64_t nchunks, int64_t t, double *const *outs,
-                               bool recursion, hipStream_t s) {
+                               bool recursion, hipStream_t s, double *const *moms = nullptr) {
     cum_status st = upload_plan(*c);
     if (st) return st;
     // in pairs of orders {d, d+1}: order d needs cumulants up to d-2 only, so
@@ -911,8 +937,11 @@ static cum_status run_finalize(CallPlan *c, double *sums, int64_t nchunks, int64
         ra.set0.stride = c->stride;
         ra.set0.nchunks = nchunks;
         ra.set0.t = t;
-        for (int k = 0; k < MAXD - 1; ++k) ra.set0.kappa[k] = nullptr;
+        for (int k = 0; k < MAXD - 1; ++k) ra.set0.kappa[k] = ra.set0.mom[k] = nullptr;
         for (int dd = c->dlo; dd <= c->dhi; ++dd) ra.set0.kappa[dd - 2] = outs[dd - c->dlo];
+        ra.subset = (recursion && moms && c->dlo == 2 && c->dhi >= FIRST_POSITION_MIN_D) ? 1 : 0;
+        if (ra.subset)
+            for (int m = 2; m <= c->dhi - 2; ++m) ra.set0.mom[m - 2] = moms[m - 2];
         ra.set0.stamp = nullptr;
         if (!recursion) {
             // plain moments: no order reads another, one launch for all
@@ -940,11 +969,21 @@ static cum_status run_finalize(CallPlan *c, double *sums, int64_t nchunks, int64
 // moment contraction + reduction for orders dlo..dhi into outs (and the
 // recursion for d >= 4 when recursion is set)
 static cum_status run_orders(const Call &k, const void *Xc, double *partial, double *const *outs, bool recursion,
-                             hipStream_t s) {
+                             hipStream_t s, double *const *moms = nullptr) {
     cum_status st;
     bool summed;
     if ((st = run_contraction(k, Xc, partial, false, &summed, s))) return st;
-    return run_finalize(k.c, partial, summed ? 1 : k.nchunks, k.t, outs, recursion, s);
+    return run_finalize(k.c, partial, summed ? 1 : k.nchunks, k.t, outs, recursion, s, moms);
+}
+
+// Bytes of the central-moment buffers the first-position formula needs
+// (orders 2..d_max-2 in block storage), 0 below order 7.
+static size_t moment_bytes(int n, int b, int d_max) {
+    if (d_max < FIRST_POSITION_MIN_D) return 0;
+    size_t total = 0;
+    const int64_t nbar = (n + b - 1) / b;
+    for (int m = 2; m <= d_max - 2; ++m) total += align_up((size_t)(binom(nbar + m - 1, m) * ipow64(b, m)) * 8);
+    return total;
 }
 
 }  // namespace cum
@@ -1023,7 +1062,7 @@ cum_status cum_workspace_size(int64_t t, int n, int d_max, int b, cum_prec prec,
         if ((st = get_call(n, b, d, d, prec, t, &k1))) return st;
         part = std::max(part, (size_t)k1.nchunks * k1.c->stride * 8);
     }
-    *bytes = total + align_up(part);
+    *bytes = total + align_up(part) + moment_bytes(n, b, d_max);
     return CUM_OK;
 }
 
@@ -1091,7 +1130,7 @@ cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_m
     const size_t cbytes = align_up((size_t)groups * n * 2 * 8);
     const size_t mbytes = align_up((size_t)n * 8);
     const size_t pbytes = align_up((size_t)k.nchunks * k.c->stride * 8);
-    const size_t need = xbytes + cbytes + mbytes + pbytes;
+    const size_t need = xbytes + cbytes + mbytes + pbytes + moment_bytes(n, b, d_max);
     if (!ws || ws_bytes < need) return fail(CUM_ENOMEM, "cumulants needs %zu workspace bytes (got %zu)", need, ws_bytes);
     char *w = (char *)ws;
     char *Xst = w;
@@ -1103,7 +1142,19 @@ cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_m
     if ((st = upload_call(k))) return st;
     if ((st = center_impl(X, t, n, ldx, prec, mu, nullptr, cw, cbytes, s))) return st;
     HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, mu, Xst, prec, true, true, s); }));
-    return run_orders(k, Xst, partial, kappa, true, s);
+    // central moments of the lower orders for the first-position formula
+    double *moms[MAXD - 1] = {nullptr};
+    double *const *mp = nullptr;
+    if (d_max >= FIRST_POSITION_MIN_D) {
+        char *mw = w + xbytes + cbytes + mbytes + pbytes;
+        const int64_t nbar = (n + b - 1) / b;
+        for (int m = 2; m <= d_max - 2; ++m) {
+            moms[m - 2] = (double *)mw;
+            mw += align_up((size_t)(binom(nbar + m - 1, m) * ipow64(b, m)) * 8);
+        }
+        mp = moms;
+    }
+    return run_orders(k, Xst, partial, kappa, true, s, mp);
 }
 
 cum_status cum_unfold(const double *blocks, int n, int d, int b, double *dense, void *stream) {
@@ -1202,6 +1253,35 @@ cum_status cum_plan_check(int n, int d, int b) {
                 return fail(CUM_EINVAL, "d=%d: partition %d does not cover the positions", d, z);
             std::sort(masks.begin(), masks.end());
             if (!seen.insert(masks).second) return fail(CUM_EINVAL, "d=%d: partition %d repeated", d, z);
+        }
+        // first-position terms (orders >= 7): every set A holding position 0
+        // with 2..d-2 positions once (2^(d-1) - d - 1 of them), each with its
+        // complement, both located like the parts above
+        const int want_terms = d >= FIRST_POSITION_MIN_D ? (1 << (d - 1)) - d - 1 : 0;
+        if (o.nterm != want_terms || (int)o.terms.size() != 2 * want_terms)
+            return fail(CUM_EINVAL, "d=%d: %d first-position terms, expected %d", d, o.nterm, want_terms);
+        std::set<int> seen_a;
+        for (int z = 0; z < o.nterm; ++z) {
+            int masks2[2];
+            for (int k = 0; k < 2; ++k) {
+                const int32_t v = o.terms[(size_t)z * 2 + k];
+                const unsigned mask = (unsigned)v & 1023u;
+                const int where = v >> 10, m = __builtin_popcount(mask);
+                if (m < 2 || m > d - 2) return fail(CUM_EINVAL, "d=%d: bad set in term %d", d, z);
+                const size_t si = (size_t)(std::find(o.smask.begin(), o.smask.end(), (uint16_t)mask) - o.smask.begin());
+                if (si >= o.smask.size()) return fail(CUM_EINVAL, "d=%d: term set missing from the set list", d);
+                if (o.lds_elems) {
+                    if (where < 0 || where >= o.lds_elems || (o.gmap[(size_t)where] & 1023) != (int32_t)si ||
+                        (o.gmap[(size_t)where] >> 10) != 0)
+                        return fail(CUM_EINVAL, "d=%d: staged offset of factor %d of term %d", d, k, z);
+                } else if (where != (int)si) {
+                    return fail(CUM_EINVAL, "d=%d: set index of factor %d of term %d", d, k, z);
+                }
+                masks2[k] = (int)mask;
+            }
+            if (!(masks2[0] & 1) || (masks2[0] ^ masks2[1]) != (1 << d) - 1 || (masks2[0] & masks2[1]))
+                return fail(CUM_EINVAL, "d=%d: term %d is not a set with position 0 and its complement", d, z);
+            if (!seen_a.insert(masks2[0]).second) return fail(CUM_EINVAL, "d=%d: term %d repeated", d, z);
         }
         // staged slots: each set's sub-block in order, grouped by set size
         if (o.lds_elems) {
@@ -1689,7 +1769,8 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
         p->sets[s].X = c.Xc;
         SetRed &r = p->setred[s];
         r.t = p->t[s];
-        for (int k = 0; k < MAXD - 1; ++k) r.kappa[k] = nullptr;
+        // no central-moment buffers: batches keep the partition recursion
+        for (int k = 0; k < MAXD - 1; ++k) r.kappa[k] = r.mom[k] = nullptr;
         r.stamp = (unsigned long long *)p->stamps_d.p + 1 + s;
     }
     int64_t max_nst = 1;
@@ -1859,6 +1940,7 @@ struct cum_stream {
     std::vector<int64_t> off;  // offset of order d in the sums (index d - 2)
     CallPlan *last = nullptr;  // a plan of the window's shape (its finalisation records)
     DevBuf shift_d, s1_d, delta_d, bmean_d, sums_d, central_d, ws_d;
+    DevBuf mom_d;           // central moments of orders 2..d_max-2 for the first-position formula (d_max >= 7)
     size_t ws_bytes = 0;
 };
 
@@ -1890,6 +1972,7 @@ cum_status cum_stream_create(int n, int d_max, int b, cum_prec prec, const doubl
     HIP_TRY(hipMalloc(&p->s1_d.p, nb));
     HIP_TRY(hipMalloc(&p->delta_d.p, nb));
     HIP_TRY(hipMalloc(&p->bmean_d.p, nb));
+    if (const size_t mb = moment_bytes(n, b, d_max)) HIP_TRY(hipMalloc(&p->mom_d.p, mb));
     HIP_TRY(hipMemset(p->sums_d.p, 0, sb));
     HIP_TRY(hipMemset(p->s1_d.p, 0, nb));
     if (shift) {
@@ -1996,7 +2079,16 @@ cum_status cum_stream_cumulants(cum_stream *p, double *mean, double *const *kapp
         HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_recentre(ra, s); }));
     }
     // the central moments are already divided by t
-    return run_finalize(p->last, (double *)p->central_d.p, 1, 1, kappa, true, s);
+    double *moms[MAXD - 1] = {nullptr};
+    if (p->mom_d.p) {
+        char *mw = (char *)p->mom_d.p;
+        const int64_t nbar = (p->n + p->b - 1) / p->b;
+        for (int m = 2; m <= p->d_max - 2; ++m) {
+            moms[m - 2] = (double *)mw;
+            mw += align_up((size_t)(binom(nbar + m - 1, m) * ipow64(p->b, m)) * 8);
+        }
+    }
+    return run_finalize(p->last, (double *)p->central_d.p, 1, 1, kappa, true, s, p->mom_d.p ? moms : nullptr);
 }
 
 // device tables of all_partitions, per order

@@ -809,6 +809,19 @@ __device__ __forceinline__ double *kappa_of(const SetRed &sr, int m) {
     }
 }
 
+// mom[m - 2] likewise
+__device__ __forceinline__ double *mom_of(const SetRed &sr, int m) {
+    switch (m) {
+        case 2: return sr.mom[0];
+        case 3: return sr.mom[1];
+        case 4: return sr.mom[2];
+        case 5: return sr.mom[3];
+        case 6: return sr.mom[4];
+        case 7: return sr.mom[5];
+        default: return sr.mom[6];
+    }
+}
+
 template <int D, int NT>
 __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder &ro, const SetRed &sr, int64_t B,
                                                char *dyn, int *tup) {
@@ -820,6 +833,11 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
     for (int k = 0; k < D; ++k) be *= b;
     const bool rec = a.recursion && D >= 4;
     const bool staged = rec && ro.lds_elems > 0;
+    // orders >= 7 with the lower central moments at hand: the first-position
+    // formula (two factors per term, a set A holding position 0 and its
+    // complement); the staged slots of sets without position 0 then hold
+    // moments, the others cumulants
+    const bool first_pos = D >= FIRST_POSITION_MIN_D && rec && a.subset && ro.nterm > 0;
     double *sub = reinterpret_cast<double *>(dyn);
     int64_t *base = reinterpret_cast<int64_t *>(dyn + a.base_off);
     int32_t *parts_l = reinterpret_cast<int32_t *>(dyn + a.parts_off);
@@ -829,8 +847,13 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
 
     __syncthreads();  // the previous block's readers are done with the LDS tables
     if (tid < D) tup[tid] = gmem(ro.tuples)[B * D + tid];
-    if (parts_in_lds)
-        for (int i = tid; i < ro.npart * PARTS; i += NT) parts_l[i] = parts_g[i];
+    const CUM_GLOBAL int32_t *terms_g = gmem(ro.terms);
+    if (parts_in_lds) {
+        if (first_pos)
+            for (int i = tid; i < ro.nterm * 2; i += NT) parts_l[i] = terms_g[i];
+        else
+            for (int i = tid; i < ro.npart * PARTS; i += NT) parts_l[i] = parts_g[i];
+    }
     __syncthreads();
     if (rec) {
         // block offset of j_S in the order-|S| layout: the rank of the sorted
@@ -859,9 +882,11 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
 #pragma unroll
         for (int m = 2; m <= D - 2; ++m) {
             const CUM_GLOBAL double *kp = gmem(sr.kappa[m - 2]);
+            const CUM_GLOBAL double *mp = first_pos ? gmem(sr.mom[m - 2]) : kp;
             for (int e = ro.mstart[m - 2] + tid; e < ro.mstart[m - 1]; e += NT) {
                 const int g = gmem(ro.gmap)[e];
-                sub[e] = kp[base[g & 1023] + (g >> 10)];
+                const bool moment = first_pos && !(gmem(ro.smask)[g & 1023] & 1u);
+                sub[e] = (moment ? mp : kp)[base[g & 1023] + (g >> 10)];
             }
         }
         __syncthreads();
@@ -945,6 +970,48 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
         }
         // sum over partitions of products of lower cumulants; the lower-order
         // sub-blocks are in LDS (staged) or read from memory
+        // the first-position formula: sum over sets A holding position 0 of
+        // kappa(A) times the central moment of the complement
+        auto first_position = [&](auto staged_t) {
+            constexpr bool ST = decltype(staged_t)::value;
+            double sum[EPT];
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) sum[q] = 0.0;
+            for (int z = 0; z < ro.nterm; ++z) {
+                double prod[EPT];
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) prod[q] = 1.0;
+#pragma unroll
+                for (int pt = 0; pt < 2; ++pt) {
+                    const int pk = __builtin_amdgcn_readfirstlane(parts_in_lds ? parts_l[z * 2 + pt]
+                                                                               : terms_g[z * 2 + pt]);
+                    const unsigned mask = (unsigned)pk & 1023u;
+                    const int where = pk >> 10;
+                    int flat[EPT];
+#pragma unroll
+                    for (int q = 0; q < EPT; ++q) {
+                        flat[q] = 0;
+#pragma unroll
+                        for (int k = 0; k < D; ++k)
+                            if (mask >> k & 1u) flat[q] = flat[q] * (int)b + r[q][k];
+                    }
+                    if constexpr (ST) {
+#pragma unroll
+                        for (int q = 0; q < EPT; ++q) prod[q] *= sub[where + flat[q]];
+                    } else {
+                        const int m = __popc(mask);
+                        const CUM_GLOBAL double *src =
+                            gmem(pt == 0 ? kappa_of(sr, m) : mom_of(sr, m)) + base[where];
+#pragma unroll
+                        for (int q = 0; q < EPT; ++q) prod[q] *= src[flat[q]];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) sum[q] += prod[q];
+            }
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) M[q] -= sum[q];
+        };
         auto recursion = [&](auto staged_t) {
             constexpr bool ST = decltype(staged_t)::value;
             double sum[EPT];
@@ -986,10 +1053,33 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
 #pragma unroll
             for (int q = 0; q < EPT; ++q) M[q] -= sum[q];
         };
-        if (staged)
-            recursion(std::true_type());
-        else if (rec)
-            recursion(std::false_type());
+        // the central moments of this order, for the first-position formula of
+        // higher orders
+        if (sr.mom[D - 2]) {
+            CUM_GLOBAL double *mo = gmem(sr.mom[D - 2]);
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const unsigned o = o0 + (unsigned)NT * q;
+                if (o < be) mo[B * be + o] = M[q];
+            }
+        }
+        if constexpr (D >= FIRST_POSITION_MIN_D) {
+            if (first_pos) {
+                if (staged)
+                    first_position(std::true_type());
+                else
+                    first_position(std::false_type());
+            } else if (staged) {
+                recursion(std::true_type());
+            } else if (rec) {
+                recursion(std::false_type());
+            }
+        } else {
+            if (staged)
+                recursion(std::true_type());
+            else if (rec)
+                recursion(std::false_type());
+        }
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
             const unsigned o = o0 + (unsigned)NT * q;

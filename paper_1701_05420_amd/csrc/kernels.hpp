@@ -29,7 +29,8 @@ struct RedArgs {
     int32_t base_off;   // dynamic LDS layout: staged sub-blocks at 0, the block's
     int32_t parts_off;  // lower-order offsets at base_off, the partition table at
     int32_t parts_lds;  // parts_off when parts_lds (else it is read from memory)
-    int32_t pad;
+    int32_t subset;     // 1: orders >= 7 use the first-position formula (the sets hold the
+                        // central moments of every order they need)
     int64_t nb0;   // blocks of the first order
     int64_t nbtot; // blocks of all orders of the launch
     const SetRed *sets;  // per-dataset records (grid.y), or null: set0

@@ -114,11 +114,15 @@ struct RedOrder {
                              // the index of the part's position set in smask (others)
     const uint16_t *smask;   // ns position sets S of 2..d-2 positions, by size then value
     const int32_t *gmap;     // lds_elems staged slots: s | flat << 10, grouped by |S|
+    const int32_t *terms;    // orders >= 7: nterm x 2 factors (a set A holding the first position
+                             // and its complement C), packed mask | where << 10 like parts
     const int64_t *prank;    // d x (pnbar + 1) rank terms of the partial-sum layout:
                              // prank[k][x] = pb^d * C(pnbar - x + d - k - 1, d - k)
     int64_t nblocks;
     int64_t out_off;         // offset of this order in the per-chunk partial vector
     int32_t d, npart, nbar, b;
+    int32_t nterm;           // terms of the first-position formula (orders >= 7), else 0
+    int32_t pad2;
     int32_t ns;              // position sets of 2..d-2 positions
     int32_t lds_elems;       // doubles staged per block (0: lower orders read from memory)
     int32_t mstart[MAXD];    // staged slots of sets of size m start at mstart[m - 2]; mstart[d - 3] = lds_elems
@@ -126,6 +130,10 @@ struct RedOrder {
     int32_t n;               // variables
     int32_t pad;
 };
+// Smallest order whose finalisation can use the first-position form of the
+// moment-cumulant relation (when the central moments of lower orders are
+// kept); lower orders keep the partition recursion.
+constexpr int FIRST_POSITION_MIN_D = 7;
 constexpr int RED_LDS_MAX = 6144;  // doubles of lower-order sub-blocks staged per block (48 KiB)
 
 struct SetRed {
@@ -134,6 +142,9 @@ struct SetRed {
     int64_t nchunks;
     int64_t t;
     double *kappa[MAXD - 1];       // kappa[d-2]
+    double *mom[MAXD - 1];         // central moments of order d in block storage (mom[d-2]), or null:
+                                   // written by the finalisation of order d, read as factors by
+                                   // the first-position formula of orders d+2 and above
     unsigned long long *stamp;     // finalisation timestamp (or null)
 };
 

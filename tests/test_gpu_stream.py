@@ -184,3 +184,32 @@ def test_moebius_integer_exact(dev, orc, prec):
         st.add(torch.from_numpy(X).cuda())
     check_moebius(orc, st, np.concatenate(Xs), dmax, b, 0.0, exact=True)
     st.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_stream_high_order_window(dev, orc, prec):
+    """d_max = 8: the window's cumulants of orders 7 and 8 come from the
+    first-position formula over the kept central moments; against the
+    oracle's dense recursion on the window's samples."""
+    torch, pc = dev
+    n, b, dmax = 4, 3, 8
+    Xs = [workloads.laplace_mix(t=t, n=n, seed=950 + t) + 0.5 for t in (900, 700, 1100)]
+    Xd = [torch.from_numpy(X).cuda() for X in Xs]
+    st = pc.Stream(n, dmax, b, prec)
+    for X in Xd:
+        st.add(X)
+    st.remove(Xd[0])
+    say(f"high-order window prec={prec}")
+    Xw = np.concatenate(Xs[1:])
+    mean, K = st.cumulants()
+    torch.cuda.synchronize()
+    om, OK = orc.cumulants_dense(Xw, dmax)
+    assert np.abs(mean.cpu().numpy() - om).max() <= 1e-13 * max(1.0, np.abs(Xw).max())
+    tol = 1e-10 if prec == "f64" else 1e-6
+    for d in range(2, dmax + 1):
+        want = orc.fold(OK[d], b)
+        s_d = (np.abs(Xw - om) ** d).mean(axis=0).max()
+        e = np.abs(K[d].cpu().numpy() - want).max() / max(np.abs(want).max(), s_d)
+        say(f"  e_{d} = {e:.3e}")
+        assert e <= tol, (d, e)
+    st.close()
