@@ -102,8 +102,9 @@ typedef struct {
 cum_status cum_layout_query(int n, int d, int b, cum_layout *out /* host */);
 
 /* Host only.  Bytes of device workspace needed by cum_cumulants(t, n, d_max,
- * b, prec); it is also enough for cum_center(t, n, prec) and for
- * cum_moment_blocks(t, n, d, b, prec) with d <= d_max. */
+ * b, prec) (from d_max = 7 on, this includes the central moments of orders
+ * 2..d_max-2 in block storage); it is also enough for cum_center(t, n, prec)
+ * and for cum_moment_blocks(t, n, d, b, prec) with d <= d_max. */
 cum_status cum_workspace_size(int64_t t, int n, int d_max, int b, cum_prec prec, size_t *bytes /* host */);
 
 /* Column means and centred data (Def. of the centred variable, Section 1.3).
@@ -127,7 +128,9 @@ cum_status cum_center(const double *X, int64_t t, int n, int64_t ldx, cum_prec p
 cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, int d, int b, double *M, void *ws,
                              size_t ws_bytes, void *stream);
 
-/* Cumulant tensors c_2..c_dmax of X (Alg. 5 for every order in turn).
+/* Cumulant tensors c_2..c_dmax of X (Alg. 5 for every order in turn; orders
+ * 7 and above use the equivalent moment-cumulant relation split at the first
+ * position, over the central moments of lower orders kept in the workspace).
  *   X      t x n FP64, leading dimension ldx >= n
  *   mean   n FP64 out (the first cumulant), or NULL
  *   kappa  (host) array of d_max-1 device pointers; kappa[d-2] receives c_d
