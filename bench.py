@@ -454,7 +454,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X (sharding across GPUs "
-              "is described in DESIGN.md but not built); run it with --gpus 1", file=sys.stderr)
+              "is not built); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
