@@ -210,3 +210,12 @@ def test_missing_library_fails_loudly(tmp_path):
                          env=dict(os.environ, PYTHONPATH=str(tmp_path)), capture_output=True, text=True, timeout=120)
     assert out.returncode != 0
     assert "ImportError" in out.stderr and "no fallback" in out.stderr
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU: --gpus 2 ends with a message, before
+    any device work."""
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU only" in out.stderr and not out.stdout
