@@ -219,3 +219,12 @@ def test_bench_refuses_more_than_one_gpu():
                          text=True, timeout=120)
     assert out.returncode == 2
     assert "one GPU only" in out.stderr and not out.stdout
+
+
+def test_workspace_holds_lower_moments_from_order_7(pc):
+    """From d_max = 7 on, the workspace also holds the central moments of
+    orders 2..d_max-2 in block storage (the first-position finalisation):
+    going from d_max = 6 to 7 adds at least those bytes."""
+    t, n, b = 20_000, 8, 2
+    lower = sum(pc.layout(n, m, b)["elems"] * 8 for m in range(2, 6))
+    assert pc.workspace_size(t, n, 7, b, "f32") >= pc.workspace_size(t, n, 6, b, "f32") + lower
