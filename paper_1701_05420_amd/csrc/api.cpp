@@ -928,6 +928,7 @@ static cum_status run_finalize(CallPlan *c, double *sums, int64_t nchunks, int64
         ra.ords = red_d + i0;
         ra.nords = (d + 1 <= c->dhi) ? 2 : 1;
         ra.d0 = d;
+        ra.b = c->red[i0].b;
         ra.recursion = recursion ? 1 : 0;
         ra.presummed = 0;
         ra.nb0 = c->red[i0].nblocks;
@@ -1694,6 +1695,7 @@ static cum_status batch_enqueue(cum_batch &p, hipStream_t s) {
         ra.ords = red_d + i0;
         ra.nords = (d + 1 <= p.d_max) ? 2 : 1;
         ra.d0 = d;
+        ra.b = p.b;
         ra.recursion = 1;
         ra.presummed = 1;
         ra.nb0 = p.red[i0].nblocks;

@@ -769,7 +769,11 @@ hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int
 // each entry reads its chunk sum, divides by t and subtracts the sum over
 // partitions of products of lower cumulants read at (j_S, i_S).  Each thread
 // takes EPT entries at a time, so that one read of a partition's parts
-// serves all of them.
+// serves all of them.  A block's entries can be cut into slices of NT * EPT
+// entries, each taken by its own work-group (which stages the block's
+// lower-order sub-blocks for itself): at high orders there are few blocks of
+// many entries, each with hundreds of terms, and one work-group per block
+// leaves most of the chip idle.
 // ---------------------------------------------------------------------------
 // Binomial coefficients C(a, r), a < MAXN + MAXD + 1, r <= MAXD, built at
 // compile time (Pascal's rule).
@@ -785,7 +789,7 @@ constexpr BinomTable make_binom_table() {
 }
 __constant__ BinomTable c_binom = make_binom_table();
 
-constexpr int EPT = 4;
+constexpr int RED_EPT = 4;  // entries per thread where a block has many work-groups' worth
 
 // Pointers read from memory are generic; these say which ones address
 // global memory, so that their accesses are global (not flat) instructions.
@@ -793,6 +797,14 @@ constexpr int EPT = 4;
 template <typename T>
 __device__ __forceinline__ CUM_GLOBAL T *gmem(T *p) {
     return (CUM_GLOBAL T *)p;
+}
+// Read-only tables that every lane reads at the same index: constant address
+// space, so that those reads are scalar loads and a wait for them is not a
+// wait for the vector loads in flight.
+#define CUM_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const CUM_CONST T *cmem(const T *p) {
+    return (const CUM_CONST T *)p;
 }
 
 // kappa[m - 2] for a wave-uniform m, by constant indices (no dynamic
@@ -822,9 +834,9 @@ __device__ __forceinline__ double *mom_of(const SetRed &sr, int m) {
     }
 }
 
-template <int D, int NT>
+template <int D, int NT, int EPT>
 __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder &ro, const SetRed &sr, int64_t B,
-                                               char *dyn, int *tup) {
+                                               int slice, int nslice, char *dyn, int *tup) {
     constexpr int PARTS = D / 2;  // parts per partition slot
     const int tid = threadIdx.x;
     const unsigned b = (unsigned)ro.b;
@@ -839,15 +851,15 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
     // moments, the others cumulants
     const bool first_pos = D >= FIRST_POSITION_MIN_D && rec && a.subset && ro.nterm > 0;
     double *sub = reinterpret_cast<double *>(dyn);
-    int64_t *base = reinterpret_cast<int64_t *>(dyn + a.base_off);
+    const double **base = reinterpret_cast<const double **>(dyn + a.base_off);
     int32_t *parts_l = reinterpret_cast<int32_t *>(dyn + a.parts_off);
     const bool parts_in_lds = rec && a.parts_lds;
-    const CUM_GLOBAL int32_t *parts_g = gmem(ro.parts);
+    const CUM_CONST int32_t *parts_g = cmem(ro.parts);
     const CUM_GLOBAL int64_t *prank = gmem(ro.prank);
 
     __syncthreads();  // the previous block's readers are done with the LDS tables
     if (tid < D) tup[tid] = gmem(ro.tuples)[B * D + tid];
-    const CUM_GLOBAL int32_t *terms_g = gmem(ro.terms);
+    const CUM_CONST int32_t *terms_g = cmem(ro.terms);
     if (parts_in_lds) {
         if (first_pos)
             for (int i = tid; i < ro.nterm * 2; i += NT) parts_l[i] = terms_g[i];
@@ -856,8 +868,10 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
     }
     __syncthreads();
     if (rec) {
-        // block offset of j_S in the order-|S| layout: the rank of the sorted
-        // tuple j_S (sum of the hockey-stick rank terms) times b^|S|
+        // address of the sub-block j_S: in the order-|S| buffer (the cumulants,
+        // or the central moments for a first-position factor without position
+        // 0) at the rank of the sorted tuple j_S (sum of the hockey-stick rank
+        // terms) times b^|S|
         for (int s = tid; s < ro.ns; s += NT) {
             const unsigned mask = gmem(ro.smask)[s];
             const int m = __popc(mask);
@@ -872,22 +886,16 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
                     ++k2;
                     bm *= b;
                 }
-            base[s] = rank * bm;
+            const bool moment = first_pos && !(mask & 1u);
+            base[s] = (moment ? mom_of(sr, m) : kappa_of(sr, m)) + rank * bm;
         }
         __syncthreads();
     }
     if (staged) {
-        // the block's lower-order sub-blocks into LDS, by size of S (the
-        // cumulant array of each size is a separate buffer)
-#pragma unroll
-        for (int m = 2; m <= D - 2; ++m) {
-            const CUM_GLOBAL double *kp = gmem(sr.kappa[m - 2]);
-            const CUM_GLOBAL double *mp = first_pos ? gmem(sr.mom[m - 2]) : kp;
-            for (int e = ro.mstart[m - 2] + tid; e < ro.mstart[m - 1]; e += NT) {
-                const int g = gmem(ro.gmap)[e];
-                const bool moment = first_pos && !(gmem(ro.smask)[g & 1023] & 1u);
-                sub[e] = (moment ? mp : kp)[base[g & 1023] + (g >> 10)];
-            }
+        // the block's lower-order sub-blocks into LDS
+        for (int e = tid; e < ro.lds_elems; e += NT) {
+            const int g = gmem(ro.gmap)[e];
+            sub[e] = gmem(base[g & 1023])[g >> 10];
         }
         __syncthreads();
     }
@@ -904,7 +912,7 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
 #pragma unroll
     for (int k = 0; k + 1 < D; ++k) need_sort |= tup[k] == tup[k + 1];
 
-    for (unsigned o0 = tid; o0 < be; o0 += NT * EPT) {
+    for (unsigned o0 = (unsigned)(slice * NT * EPT + tid); o0 < be; o0 += (unsigned)(NT * EPT * nslice)) {
         int r[EPT][D];  // in-block digits, first position most significant
         double M[EPT];
 #pragma unroll
@@ -968,84 +976,109 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
             }
             M[q] = S / tt;
         }
-        // sum over partitions of products of lower cumulants; the lower-order
-        // sub-blocks are in LDS (staged) or read from memory
-        // the first-position formula: sum over sets A holding position 0 of
-        // kappa(A) times the central moment of the complement
-        auto first_position = [&](auto staged_t) {
+        // One factor of a term for every entry of the thread: the lower-order
+        // sub-block of part pk (position mask | where << 10), read in LDS
+        // (staged) or in memory, where first-position formula factors without
+        // position 0 are central moments.  The part is the same for every lane:
+        // readfirstlane makes that explicit, so that the position tests are
+        // scalar.
+        auto factor = [&](auto staged_t, int pk0, double (&v)[EPT]) {
             constexpr bool ST = decltype(staged_t)::value;
+            const int pk = __builtin_amdgcn_readfirstlane(pk0);
+            const unsigned mask = (unsigned)pk & 1023u;
+            const int where = pk >> 10;
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                int flat = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    if (mask >> k & 1u) flat = flat * (int)b + r[q][k];
+                if constexpr (ST)
+                    v[q] = sub[where + flat];
+                else
+                    v[q] = gmem(base[where])[flat];
+            }
+        };
+        auto part_at = [&](const CUM_CONST int32_t *table, int i) {
+            return __builtin_amdgcn_readfirstlane(parts_in_lds ? parts_l[i] : table[i]);
+        };
+        // the first-position formula: sum over sets A holding position 0 of
+        // kappa(A) times the central moment of the complement, in term order
+        auto first_position = [&](auto staged_t) {
             double sum[EPT];
 #pragma unroll
             for (int q = 0; q < EPT; ++q) sum[q] = 0.0;
-            for (int z = 0; z < ro.nterm; ++z) {
-                double prod[EPT];
+            int z = 0;
+            if constexpr (EPT == 1) {
+                // one entry per thread: four terms' parts in one scalar read,
+                // then their eight loads in flight at once
+                for (; z + 4 <= ro.nterm; z += 4) {
+                    int pk[8];
 #pragma unroll
-                for (int q = 0; q < EPT; ++q) prod[q] = 1.0;
+                    for (int i = 0; i < 8; ++i) pk[i] = terms_g[z * 2 + i];
+                    double v[8][EPT];
 #pragma unroll
-                for (int pt = 0; pt < 2; ++pt) {
-                    const int pk = __builtin_amdgcn_readfirstlane(parts_in_lds ? parts_l[z * 2 + pt]
-                                                                               : terms_g[z * 2 + pt]);
-                    const unsigned mask = (unsigned)pk & 1023u;
-                    const int where = pk >> 10;
-                    int flat[EPT];
+                    for (int i = 0; i < 8; ++i) factor(staged_t, pk[i], v[i]);
 #pragma unroll
-                    for (int q = 0; q < EPT; ++q) {
-                        flat[q] = 0;
-#pragma unroll
-                        for (int k = 0; k < D; ++k)
-                            if (mask >> k & 1u) flat[q] = flat[q] * (int)b + r[q][k];
-                    }
-                    if constexpr (ST) {
-#pragma unroll
-                        for (int q = 0; q < EPT; ++q) prod[q] *= sub[where + flat[q]];
-                    } else {
-                        const int m = __popc(mask);
-                        const CUM_GLOBAL double *src =
-                            gmem(pt == 0 ? kappa_of(sr, m) : mom_of(sr, m)) + base[where];
-#pragma unroll
-                        for (int q = 0; q < EPT; ++q) prod[q] *= src[flat[q]];
-                    }
+                    for (int u = 0; u < 4; ++u) sum[0] += v[2 * u][0] * v[2 * u + 1][0];
                 }
+            }
+            for (; z < ro.nterm; ++z) {
+                double v0[EPT], v1[EPT];
+                factor(staged_t, part_at(terms_g, z * 2), v0);
+                factor(staged_t, part_at(terms_g, z * 2 + 1), v1);
 #pragma unroll
-                for (int q = 0; q < EPT; ++q) sum[q] += prod[q];
+                for (int q = 0; q < EPT; ++q) sum[q] += v0[q] * v1[q];
             }
 #pragma unroll
             for (int q = 0; q < EPT; ++q) M[q] -= sum[q];
         };
+        // sum over partitions of products of lower cumulants, in partition
+        // order; a partition's row ends at its first zero part
         auto recursion = [&](auto staged_t) {
-            constexpr bool ST = decltype(staged_t)::value;
             double sum[EPT];
 #pragma unroll
             for (int q = 0; q < EPT; ++q) sum[q] = 0.0;
-            for (int z = 0; z < ro.npart; ++z) {
+            int z = 0;
+            if constexpr (EPT == 1) {
+                for (; z + 4 <= ro.npart; z += 4) {
+                    int pks[4 * PARTS];
+#pragma unroll
+                    for (int i = 0; i < 4 * PARTS; ++i) pks[i] = parts_g[z * PARTS + i];
+                    double prod[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        double v[PARTS][EPT];
+                        bool live = true;
+#pragma unroll
+                        for (int pt = 0; pt < PARTS; ++pt) {
+                            const int pk = __builtin_amdgcn_readfirstlane(pks[u * PARTS + pt]);
+                            live = live && pk != 0;
+                            if (live)
+                                factor(staged_t, pk, v[pt]);
+                            else
+                                v[pt][0] = 1.0;
+                        }
+                        prod[u] = 1.0;
+#pragma unroll
+                        for (int pt = 0; pt < PARTS; ++pt) prod[u] *= v[pt][0];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) sum[0] += prod[u];
+                }
+            }
+            for (; z < ro.npart; ++z) {
                 double prod[EPT];
 #pragma unroll
                 for (int q = 0; q < EPT; ++q) prod[q] = 1.0;
 #pragma unroll
                 for (int pt = 0; pt < PARTS; ++pt) {
-                    // the same part for every lane: make that explicit, so that the
-                    // position tests below are scalar
-                    const int pk = __builtin_amdgcn_readfirstlane(parts_in_lds ? parts_l[z * PARTS + pt]
-                                                                               : parts_g[z * PARTS + pt]);
+                    const int pk = part_at(parts_g, z * PARTS + pt);
                     if (!pk) break;
-                    const unsigned mask = (unsigned)pk & 1023u;
-                    const int where = pk >> 10;
-                    int flat[EPT];
+                    double v[EPT];
+                    factor(staged_t, pk, v);
 #pragma unroll
-                    for (int q = 0; q < EPT; ++q) {
-                        flat[q] = 0;
-#pragma unroll
-                        for (int k = 0; k < D; ++k)
-                            if (mask >> k & 1u) flat[q] = flat[q] * (int)b + r[q][k];
-                    }
-                    if constexpr (ST) {
-#pragma unroll
-                        for (int q = 0; q < EPT; ++q) prod[q] *= sub[where + flat[q]];
-                    } else {
-                        const CUM_GLOBAL double *src = gmem(kappa_of(sr, __popc(mask))) + base[where];
-#pragma unroll
-                        for (int q = 0; q < EPT; ++q) prod[q] *= src[flat[q]];
-                    }
+                    for (int q = 0; q < EPT; ++q) prod[q] *= v[q];
                 }
 #pragma unroll
                 for (int q = 0; q < EPT; ++q) sum[q] += prod[q];
@@ -1089,22 +1122,25 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
     if (sr.stamp && tid == 0) atomicMax(sr.stamp, (unsigned long long)wall_clock64());
 }
 
-// NT threads per work-group: 256, or one wave (64) when the blocks are small
-// (b^d <= 256), so that more blocks are in flight per compute unit.
-template <int D0, int NT>
+// NT threads per work-group: 256, or one wave (64) when the blocks are small,
+// so that more blocks are in flight per compute unit.  Work-group g takes
+// slice g % sl of block g / sl of its order (sl0 or sl1 slices per block).
+template <int D0, int NT, int EPT>
 __global__ __launch_bounds__(NT) void reduce_kernel(RedArgs a) {
     extern __shared__ __align__(16) char dyn[];
     __shared__ int tup[MAXD];
     SetRed sr = a.set0;
     if (a.sets) sr = a.sets[blockIdx.y];
-    for (int64_t gb = blockIdx.x; gb < a.nbtot; gb += gridDim.x) {
-        if (gb < a.nb0) {
+    const int64_t n0 = a.nb0 * a.sl0, ntot = n0 + (a.nbtot - a.nb0) * a.sl1;
+    for (int64_t g = blockIdx.x; g < ntot; g += gridDim.x) {
+        if (g < n0) {
             const RedOrder ro = a.ords[0];
-            finalize_block<D0, NT>(a, ro, sr, gb, dyn, tup);
+            finalize_block<D0, NT, EPT>(a, ro, sr, g / a.sl0, (int)(g % a.sl0), a.sl0, dyn, tup);
         } else {
             if constexpr (D0 < MAXD) {
                 const RedOrder ro = a.ords[1];
-                finalize_block<D0 + 1, NT>(a, ro, sr, gb - a.nb0, dyn, tup);
+                const int64_t h = g - n0;
+                finalize_block<D0 + 1, NT, EPT>(a, ro, sr, h / a.sl1, (int)(h % a.sl1), a.sl1, dyn, tup);
             }
         }
     }
@@ -1142,31 +1178,60 @@ hipError_t launch_chunksum(const SetRed *sets, const SetRed &set0, int nsets, in
     return hipGetLastError();
 }
 
-template <int NT>
+template <int NT, int EPT>
 static void launch_reduce_nt(const RedArgs &a, dim3 grid, int lds_bytes, hipStream_t s) {
     const dim3 block(NT);
+    if constexpr (EPT == 1) {
+        // launches whose top order is 7 or more
+        switch (a.d0) {
+            case 6: hipLaunchKernelGGL((reduce_kernel<6, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+            case 7: hipLaunchKernelGGL((reduce_kernel<7, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+            case 8: hipLaunchKernelGGL((reduce_kernel<8, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+            case 9: hipLaunchKernelGGL((reduce_kernel<9, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+            default: hipLaunchKernelGGL((reduce_kernel<10, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+        }
+        return;
+    }
     switch (a.d0) {
-        case 2: hipLaunchKernelGGL((reduce_kernel<2, NT>), grid, block, (size_t)lds_bytes, s, a); break;
-        case 3: hipLaunchKernelGGL((reduce_kernel<3, NT>), grid, block, (size_t)lds_bytes, s, a); break;
-        case 4: hipLaunchKernelGGL((reduce_kernel<4, NT>), grid, block, (size_t)lds_bytes, s, a); break;
-        case 5: hipLaunchKernelGGL((reduce_kernel<5, NT>), grid, block, (size_t)lds_bytes, s, a); break;
-        case 6: hipLaunchKernelGGL((reduce_kernel<6, NT>), grid, block, (size_t)lds_bytes, s, a); break;
-        case 7: hipLaunchKernelGGL((reduce_kernel<7, NT>), grid, block, (size_t)lds_bytes, s, a); break;
-        case 8: hipLaunchKernelGGL((reduce_kernel<8, NT>), grid, block, (size_t)lds_bytes, s, a); break;
-        case 9: hipLaunchKernelGGL((reduce_kernel<9, NT>), grid, block, (size_t)lds_bytes, s, a); break;
-        default: hipLaunchKernelGGL((reduce_kernel<10, NT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 2: hipLaunchKernelGGL((reduce_kernel<2, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 3: hipLaunchKernelGGL((reduce_kernel<3, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 4: hipLaunchKernelGGL((reduce_kernel<4, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 5: hipLaunchKernelGGL((reduce_kernel<5, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 6: hipLaunchKernelGGL((reduce_kernel<6, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 7: hipLaunchKernelGGL((reduce_kernel<7, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 8: hipLaunchKernelGGL((reduce_kernel<8, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+        case 9: hipLaunchKernelGGL((reduce_kernel<9, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
+        default: hipLaunchKernelGGL((reduce_kernel<10, NT, EPT>), grid, block, (size_t)lds_bytes, s, a); break;
     }
 }
 
-hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, int block_elems, hipStream_t s) {
-    if (a.d0 < 2 || a.d0 > MAXD) return hipErrorInvalidValue;
-    int64_t gx = a.nbtot;
+// With the recursion up to order 7 and beyond, every entry runs 56 to 501
+// terms, and the blocks are few: one entry per thread, and a block's entries
+// over as many work-groups as it fills.  Elsewhere four entries per thread
+// and one work-group per block.
+hipError_t launch_reduce(const RedArgs &a0, int nsets, int lds_bytes, int block_elems, hipStream_t s) {
+    if (a0.d0 < 2 || a0.d0 > MAXD || block_elems < 1) return hipErrorInvalidValue;
+    RedArgs a = a0;
+    const int top = a.d0 + (a.nords == 2 ? 1 : 0);
+    const bool wide = a.recursion && top >= FIRST_POSITION_MIN_D && a.d0 >= 6;
+    const int nt = wide ? (block_elems >= 256 ? 256 : 64) : (block_elems <= 64 * RED_EPT ? 64 : 256);
+    const int64_t be1 = (int64_t)block_elems * a.b;  // entries per block of order d0 + 1
+    a.sl0 = wide ? (int32_t)((block_elems + nt - 1) / nt) : 1;
+    a.sl1 = wide ? (int32_t)((be1 + nt - 1) / nt) : 1;
+    int64_t gx = a.nb0 * a.sl0 + (a.nbtot - a.nb0) * a.sl1;
     if (gx > 65535) gx = 65535;
+    if (gx < 1) gx = 1;
     const dim3 grid((unsigned)gx, (unsigned)nsets);
-    if (block_elems <= 64 * EPT)
-        launch_reduce_nt<64>(a, grid, lds_bytes, s);
-    else
-        launch_reduce_nt<256>(a, grid, lds_bytes, s);
+    if (wide) {
+        if (nt == 64)
+            launch_reduce_nt<64, 1>(a, grid, lds_bytes, s);
+        else
+            launch_reduce_nt<256, 1>(a, grid, lds_bytes, s);
+    } else if (nt == 64) {
+        launch_reduce_nt<64, RED_EPT>(a, grid, lds_bytes, s);
+    } else {
+        launch_reduce_nt<256, RED_EPT>(a, grid, lds_bytes, s);
+    }
     return hipGetLastError();
 }
 

@@ -31,6 +31,9 @@ struct RedArgs {
     int32_t parts_lds;  // parts_off when parts_lds (else it is read from memory)
     int32_t subset;     // 1: orders >= 7 use the first-position formula (the sets hold the
                         // central moments of every order they need)
+    int32_t b;          // block size (a block of order d holds b^d entries)
+    int32_t sl0, sl1;   // work-groups per block of each order (set by the launch)
+    int32_t pad;
     int64_t nb0;   // blocks of the first order
     int64_t nbtot; // blocks of all orders of the launch
     const SetRed *sets;  // per-dataset records (grid.y), or null: set0
