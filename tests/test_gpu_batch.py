@@ -117,3 +117,45 @@ def test_batch_workload_sampled(dev, orc):
                 want = orc.cumulant_at(Xc, idx)
                 assert rel(K[s][d].cpu().numpy()[offs], want) <= TOL["f32"]
     batch.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_high_order_integer_exact(dev, orc, prec):
+    """Batches keep the partition recursion at every order: orders to 9, with
+    its 3425-partition table, bit-exact on small-integer data."""
+    torch, pc = dev
+    n, b, dmax = 3, 2, 9
+    ts = [64, 32, 128, 16]
+    say(f"batch high-order integer prec={prec} n={n} b={b} d_max={dmax}")
+    Xs = [workloads.dyadic_integers(t=t, n=n, seed=40 + t, lo=-1, hi=1) for t in ts]
+    Xd = [torch.from_numpy(X).cuda() for X in Xs]
+    batch = pc.Batch(ts, n, dmax, b, prec)
+    _, K = batch.run(Xd)
+    torch.cuda.synchronize()
+    for s, X in enumerate(Xs):
+        _, OK = orc.cumulants_dense(X, dmax)
+        for d in range(2, dmax + 1):
+            got = K[s][d].cpu().numpy()
+            want = orc.fold(OK[d], b)
+            assert np.array_equal(got, want), (s, d, np.abs(got - want).max())
+    batch.close()
+
+
+def test_batch_high_order_float(dev, orc):
+    """Orders to 8 over ragged blocks (b = 3 does not divide n = 4) on
+    floating-point data, FP64 path."""
+    torch, pc = dev
+    n, b, dmax = 4, 3, 8
+    ts = [700, 1500, 65, 2000]
+    say(f"batch high-order float n={n} b={b} d_max={dmax}")
+    Xs = [workloads.t_gamma_mix(t=t, n=n, seed=300 + i) for i, t in enumerate(ts)]
+    Xd = [torch.from_numpy(X).cuda() for X in Xs]
+    batch = pc.Batch(ts, n, dmax, b, "f64")
+    _, K = batch.run(Xd)
+    torch.cuda.synchronize()
+    for s, X in enumerate(Xs):
+        _, OK = orc.cumulants_dense(X, dmax)
+        for d in range(2, dmax + 1):
+            e = rel(K[s][d].cpu().numpy(), orc.fold(OK[d], b))
+            assert e <= 1e-10, (s, d, e)
+    batch.close()
