@@ -789,6 +789,7 @@ constexpr BinomTable make_binom_table() {
 }
 __constant__ BinomTable c_binom = make_binom_table();
 
+static_assert(MAXD <= 10, "the 24-bit sub-block index products of the finalisation assume orders up to 10");
 constexpr int RED_EPT = 4;  // entries per thread where a block has many work-groups' worth
 
 // Pointers read from memory are generic; these say which ones address
@@ -987,12 +988,18 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
             const int pk = __builtin_amdgcn_readfirstlane(pk0);
             const unsigned mask = (unsigned)pk & 1023u;
             const int where = pk >> 10;
+            // In-block index of the sub-block entry, by Horner's rule over the
+            // digits of the set's positions.  A set has at most D - 2
+            // positions, so every product below is of a value under b^(D-3)
+            // by b; with blocks under 2^31 entries (b^D < 2^31, D <= 10)
+            // b^(D-3) stays under 2^24, and the 24-bit multiply-add, a full
+            // rate vector instruction, is exact.
 #pragma unroll
             for (int q = 0; q < EPT; ++q) {
-                int flat = 0;
+                unsigned flat = 0;
 #pragma unroll
                 for (int k = 0; k < D; ++k)
-                    if (mask >> k & 1u) flat = flat * (int)b + r[q][k];
+                    if (mask >> k & 1u) flat = __umul24(flat, b) + (unsigned)r[q][k];
                 if constexpr (ST)
                     v[q] = sub[where + flat];
                 else
