@@ -790,7 +790,7 @@ constexpr BinomTable make_binom_table() {
 __constant__ BinomTable c_binom = make_binom_table();
 
 static_assert(MAXD <= 10, "the 24-bit sub-block index products of the finalisation assume orders up to 10");
-constexpr int RED_EPT = 4;  // entries per thread where a block has many work-groups' worth
+constexpr int RED_EPT = 4;  // entries per thread of launches below order 7 (one work-group per block)
 
 // Pointers read from memory are generic; these say which ones address
 // global memory, so that their accesses are global (not flat) instructions.
