@@ -78,3 +78,26 @@ def test_high_order_float_sampled(dev, orc, prec, n, b, dmax):
         e = np.abs(got - want).max() / max(np.abs(want).max(), s_d)
         say(f"  e_{d} = {e:.3e}")
         assert e <= TOL[prec], (d, e)
+
+
+def test_high_order_many_blocks(dev, orc):
+    """n = 16, b = 2, d <= 10: order 10 has 19448 blocks of 1024 entries, cut
+    into four work-groups each, more than one launch row of work-groups
+    holds (65535), so work-groups take several slices in turn.  FP32 path,
+    sampled against the oracle's per-entry route."""
+    torch, pc = dev
+    n, b, dmax = 16, 2, 10
+    X = workloads.laplace_mix(t=2000, n=n, seed=77)
+    say(f"high order many blocks n={n} b={b} dmax={dmax}")
+    _, K = pc.cumulants(torch.from_numpy(X).cuda(), dmax, b, "f32")
+    torch.cuda.synchronize()
+    Xc = X - X.mean(axis=0)
+    rng = np.random.default_rng(1610)
+    for d in (dmax - 1, dmax):
+        idx = np.concatenate([rng.integers(0, n, size=(64, d)), np.repeat(np.arange(n)[:, None], d, axis=1)])
+        want = orc.cumulant_at(Xc, idx.astype(np.int32))
+        got = K[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
+        s_d = (np.abs(Xc) ** d).mean(axis=0).max()
+        e = np.abs(got - want).max() / max(np.abs(want).max(), s_d)
+        say(f"  e_{d} = {e:.3e}")
+        assert e <= 1e-6, (d, e)
