@@ -1017,17 +1017,17 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
             for (int q = 0; q < EPT; ++q) sum[q] = 0.0;
             int z = 0;
             if constexpr (EPT == 1) {
-                // one entry per thread: four terms' parts in one scalar read,
-                // then their eight loads in flight at once
-                for (; z + 4 <= ro.nterm; z += 4) {
-                    int pk[8];
+                // one entry per thread: eight terms' parts in one scalar read,
+                // then their sixteen loads in flight at once
+                for (; z + 8 <= ro.nterm; z += 8) {
+                    int pk[16];
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) pk[i] = terms_g[z * 2 + i];
-                    double v[8][EPT];
+                    for (int i = 0; i < 16; ++i) pk[i] = terms_g[z * 2 + i];
+                    double v[16][EPT];
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) factor(staged_t, pk[i], v[i]);
+                    for (int i = 0; i < 16; ++i) factor(staged_t, pk[i], v[i]);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) sum[0] += v[2 * u][0] * v[2 * u + 1][0];
+                    for (int u = 0; u < 8; ++u) sum[0] += v[2 * u][0] * v[2 * u + 1][0];
                 }
             }
             for (; z < ro.nterm; ++z) {
