@@ -317,3 +317,42 @@ def test_high_orders_against_raw_moment_route(orc):
         want = exact.cumulant_moebius(Xf, idx)
         assert Fraction(float(want)) == want
         assert K[len(idx)][idx] == float(want), idx
+
+
+@pytest.mark.parametrize("n,dmax,seed", [(3, 9, 5), (2, 10, 6)])
+def test_orders_9_and_10_against_raw_moment_route(orc, n, dmax, seed):
+    """Orders 8 to 10, the top of the range the paper claims (Section 1.1):
+    the FP64 oracle (centred recursion, eq. cum_r) on shifted small-integer
+    data equals eq. cumfmom of Section 5.3 on the raw moments, evaluated
+    exactly with integers, at every sorted multi-index and at permutations
+    of some.  Every value here is a short dyadic fraction, so equality is
+    bit for bit."""
+    X = workloads.dyadic_integers(t=16, n=n, seed=seed, lo=-2, hi=3) + np.array([2.0, -1.0, 3.0][:n])
+    _, K = orc.cumulants_dense(X, dmax)
+    rng = np.random.default_rng(seed)
+    nonzero = 0
+    for d in range(dmax - 2, dmax + 1):
+        parts = exact.partition_masks(d)
+        idxs = list(itertools.combinations_with_replacement(range(n), d))
+        idxs += [tuple(rng.permutation(idxs[k])) for k in rng.choice(len(idxs), size=4, replace=False)]
+        for idx in idxs:
+            want = exact.cumulant_moebius_int(X, idx, parts)
+            assert Fraction(float(want)) == want, idx
+            assert K[d][idx] == float(want), (idx, K[d][idx], float(want))
+            nonzero += want != 0
+    assert nonzero > 20
+
+
+@pytest.mark.parametrize("d", [7, 8, 9, 10])
+def test_sampled_mode_equals_dense_high_orders(orc, d):
+    """The per-entry route (the recursion evaluated at chosen multi-indices)
+    gives the dense routine's bits at orders 7 to 10 too, on float data."""
+    n = 3 if d <= 9 else 2
+    X = workloads.laplace_mix(t=400, n=n, seed=40 + d)
+    _, K = orc.cumulants_dense(X, d)
+    _, Xc = orc.center(X)
+    rng = np.random.default_rng(d)
+    idx = np.concatenate([rng.integers(0, n, size=(40, d)), np.repeat(np.arange(n)[:, None], d, axis=1)])
+    got = orc.cumulant_at(Xc, idx)
+    want = np.array([K[d][tuple(i)] for i in idx])
+    assert np.array_equal(got, want)
