@@ -211,6 +211,18 @@ def _workspace(nbytes, ws, device):
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
 
+def _on(stream):
+    """Allocation context of a call: tensors the call allocates (its outputs
+    and a temporary workspace) belong to the stream its kernels run on, so
+    torch's caching allocator does not hand them to other work before that
+    stream is done with them."""
+    import contextlib
+
+    if stream is None:
+        return contextlib.nullcontext()
+    return _torch().cuda.stream(stream)
+
+
 def center(X, prec="f64", ws=None, stream=None):
     """Column means (FP64) and centred data (FP64 for 'f64', FP32 otherwise)."""
     torch = _torch()
@@ -219,9 +231,10 @@ def center(X, prec="f64", ws=None, stream=None):
     if X.stride(1) != 1:
         raise ValueError("X must have unit column stride")
     p = _prec(prec)
-    mean = torch.empty(n, dtype=torch.float64, device=X.device)
-    Xc = torch.empty((t, n), dtype=torch.float64 if p == 0 else torch.float32, device=X.device)
-    ws = _workspace(workspace_size(t, n, 2, 1, p), ws, X.device)
+    with _on(stream):
+        mean = torch.empty(n, dtype=torch.float64, device=X.device)
+        Xc = torch.empty((t, n), dtype=torch.float64 if p == 0 else torch.float32, device=X.device)
+        ws = _workspace(workspace_size(t, n, 2, 1, p), ws, X.device)
     _check(_lib.cum_center(X.data_ptr(), t, n, X.stride(0), p, mean.data_ptr(), Xc.data_ptr(), ws.data_ptr(),
                            ws.numel() * ws.element_size(), _stream(stream)))
     return mean, Xc
@@ -238,8 +251,9 @@ def moment_blocks(Xc, d: int, b: int, prec=None, ws=None, stream=None):
         raise ValueError("Xc must be contiguous (t x n, leading dimension n)")
     t, n = Xc.shape
     L = layout(n, d, b)
-    M = torch.empty(L["elems"], dtype=torch.float64, device=Xc.device)
-    ws = _workspace(workspace_size(t, n, d, b, p), ws, Xc.device)
+    with _on(stream):
+        M = torch.empty(L["elems"], dtype=torch.float64, device=Xc.device)
+        ws = _workspace(workspace_size(t, n, d, b, p), ws, Xc.device)
     _check(_lib.cum_moment_blocks(Xc.data_ptr(), p, t, n, d, b, M.data_ptr(), ws.data_ptr(),
                                   ws.numel() * ws.element_size(), _stream(stream)))
     return M
@@ -253,12 +267,13 @@ def cumulants(X, d_max: int, b: int, prec="f64", ws=None, out=None, stream=None)
         raise ValueError("X must have unit column stride")
     t, n = X.shape
     p = _prec(prec)
-    mean = torch.empty(n, dtype=torch.float64, device=X.device)
-    if out is None:
-        out = {d: torch.empty(layout(n, d, b)["elems"], dtype=torch.float64, device=X.device)
-               for d in range(2, d_max + 1)}
+    with _on(stream):
+        mean = torch.empty(n, dtype=torch.float64, device=X.device)
+        if out is None:
+            out = {d: torch.empty(layout(n, d, b)["elems"], dtype=torch.float64, device=X.device)
+                   for d in range(2, d_max + 1)}
+        ws = _workspace(workspace_size(t, n, d_max, b, p), ws, X.device)
     ptrs = (_VP * (d_max - 1))(*[out[d].data_ptr() for d in range(2, d_max + 1)])
-    ws = _workspace(workspace_size(t, n, d_max, b, p), ws, X.device)
     _check(_lib.cum_cumulants(X.data_ptr(), t, n, X.stride(0), d_max, b, p, mean.data_ptr(), ptrs,
                               ws.data_ptr(), ws.numel() * ws.element_size(), _stream(stream)))
     return mean, out
@@ -268,7 +283,8 @@ def unfold(blocks, n: int, d: int, b: int, stream=None):
     """Dense n^d tensor from block storage (canonical stored copy per entry)."""
     torch = _torch()
     _dev_check(blocks, torch.float64, "blocks")
-    dense = torch.empty((n,) * d, dtype=torch.float64, device=blocks.device)
+    with _on(stream):
+        dense = torch.empty((n,) * d, dtype=torch.float64, device=blocks.device)
     _check(_lib.cum_unfold(blocks.data_ptr(), n, d, b, dense.data_ptr(), _stream(stream)))
     return dense
 
@@ -293,11 +309,13 @@ class Batch:
             _dev_check(X, torch.float64, "X")
             if tuple(X.shape) != (self.t[s], self.n) or not X.is_contiguous():
                 raise ValueError(f"dataset {s} must be a contiguous {self.t[s]} x {self.n} tensor")
-        if out is None:
-            out = [{d: torch.empty(layout(self.n, d, self.b)["elems"], dtype=torch.float64, device=X_list[0].device)
-                    for d in range(2, self.d_max + 1)} for _ in range(ns)]
-        if means is None:
-            means = [torch.empty(self.n, dtype=torch.float64, device=X_list[0].device) for _ in range(ns)]
+        with _on(stream):
+            if out is None:
+                out = [{d: torch.empty(layout(self.n, d, self.b)["elems"], dtype=torch.float64,
+                                       device=X_list[0].device)
+                        for d in range(2, self.d_max + 1)} for _ in range(ns)]
+            if means is None:
+                means = [torch.empty(self.n, dtype=torch.float64, device=X_list[0].device) for _ in range(ns)]
         xs = (_VP * ns)(*[X.data_ptr() for X in X_list])
         ks = (_VP * (ns * (self.d_max - 1)))(*[out[s][d].data_ptr() for s in range(ns)
                                                  for d in range(2, self.d_max + 1)])
@@ -380,11 +398,12 @@ class Stream:
         torch = _torch()
         if method not in ("recursion", "moebius"):
             raise ValueError("method is 'recursion' or 'moebius'")
-        if out is None:
-            out = {d: torch.empty(layout(self.n, d, self.b)["elems"], dtype=torch.float64, device="cuda")
-                   for d in range(2, self.d_max + 1)}
-        if mean is None:
-            mean = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        with _on(stream):
+            if out is None:
+                out = {d: torch.empty(layout(self.n, d, self.b)["elems"], dtype=torch.float64, device="cuda")
+                       for d in range(2, self.d_max + 1)}
+            if mean is None:
+                mean = torch.empty(self.n, dtype=torch.float64, device="cuda")
         ks = (_VP * (self.d_max - 1))(*[out[d].data_ptr() for d in range(2, self.d_max + 1)])
         fn = _lib.cum_stream_cumulants if method == "recursion" else _lib.cum_stream_cumulants_moebius
         _check(fn(self._h, mean.data_ptr(), ks, _stream(stream)))

@@ -82,9 +82,14 @@ static int64_t binom(int64_t a, int64_t r) {
     return (int64_t)v;
 }
 
+// b^e for b >= 1, saturating at INT64_MAX (so that size guards on user
+// input see a too-large value rather than a wrapped one).
 static int64_t ipow64(int64_t b, int e) {
     int64_t r = 1;
-    for (int k = 0; k < e; ++k) r *= b;
+    for (int k = 0; k < e; ++k) {
+        if (b > 1 && r > INT64_MAX / b) return INT64_MAX;
+        r *= b;
+    }
     return r;
 }
 
@@ -753,6 +758,9 @@ static ItemSet *plan_items(CallPlan &c, int64_t nck) {
 
 static cum_status get_call_cfg(int n, int b, int bi, int dlo, int dhi, int prec, int shape, int target, int64_t t,
                                Call *out, int min_stages = 4) {
+    for (int d = dlo; d <= dhi; ++d)
+        if (ipow64(b, d) > INT32_MAX)
+            return fail(CUM_EUNSUPPORTED, "blocks of b^d = %d^%d entries (2^31 or more) are not supported", b, d);
     auto key = std::make_tuple(n, b, bi, dlo, dhi, prec, shape, target);
     auto it = g_calls.find(key);
     CallPlan *c;
@@ -774,8 +782,6 @@ static cum_status get_call_cfg(int n, int b, int bi, int dlo, int dhi, int prec,
         for (int d = dlo; d <= dhi; ++d) {
             OrderPlan *o, *co;
             cum_status st;
-            if (ipow64(b, d) > INT32_MAX)
-                return fail(CUM_EUNSUPPORTED, "blocks of b^d = %d^%d entries (2^31 or more) are not supported", b, d);
             if ((st = get_order(n, b, d, &o)) || (st = get_order(n, bi, d, &co))) return st;
             cp->orders.push_back(o);
             cp->corders.push_back(co);
@@ -1012,14 +1018,16 @@ cum_status cum_layout_query(int n, int d, int b, cum_layout *out) {
     if (d < 1 || d > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d must be in 1..%d (got %d)", CUM_MAX_ORDER, d);
     const int nbar = (n + b - 1) / b;
     const int64_t nb = binom(nbar + d - 1, d);
-    if (nb < 0) return fail(CUM_EINVAL, "layout size overflows");
+    const int64_t be = ipow64(b, d);
+    if (nb < 0 || be == INT64_MAX || nb > INT64_MAX / be)
+        return fail(CUM_EUNSUPPORTED, "the layout of n=%d, d=%d, b=%d overflows 64-bit sizes", n, d, b);
     out->n = n;
     out->d = d;
     out->b = b;
     out->nbar = nbar;
     out->b_last = n - b * (nbar - 1);
     out->nblocks = nb;
-    out->block_elems = ipow64(b, d);
+    out->block_elems = be;
     out->elems = nb * out->block_elems;
     return CUM_OK;
 }
@@ -1439,44 +1447,62 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     center_groups(t, groups, rows_per);
     const size_t xbytes = staged_bytes(t, n, prec), cbytes = align_up((size_t)groups * n * 2 * 8);
     const size_t mbytes = align_up((size_t)n * 8), kbytes = align_up((size_t)cands[0].c->kstride * 8);
+    // the lower central moments, so that orders >= 7 are timed with the
+    // finalisation cum_cumulants runs (the first-position form)
+    const size_t lbytes = moment_bytes(n, b, d_max);
     DevBuf ws;
-    HIP_TRY(hipMalloc(&ws.p, xbytes + cbytes + mbytes + kbytes + part_max));
+    HIP_TRY(hipMalloc(&ws.p, xbytes + cbytes + mbytes + kbytes + part_max + lbytes));
     char *w = (char *)ws.p;
     char *Xst = w, *cw = w + xbytes;
     double *mu = (double *)(w + xbytes + cbytes), *kap = (double *)(w + xbytes + cbytes + mbytes);
     double *partial = (double *)(w + xbytes + cbytes + mbytes + kbytes);
     double *outs[CUM_MAX_ORDER];
     for (int d = 2; d <= d_max; ++d) outs[d - 2] = kap + cands[0].c->out_off[d - 2];
+    double *moms[MAXD - 1] = {nullptr};
+    double *const *mp = nullptr;
+    if (lbytes) {
+        char *mw = w + xbytes + cbytes + mbytes + kbytes + part_max;
+        const int64_t nbar = (n + b - 1) / b;
+        for (int m = 2; m <= d_max - 2; ++m) {
+            moms[m - 2] = (double *)mw;
+            mw += align_up((size_t)(binom(nbar + m - 1, m) * ipow64(b, m)) * 8);
+        }
+        mp = moms;
+    }
     if ((st = center_impl(X, t, n, ldx, prec, mu, nullptr, cw, cbytes, s))) return st;
     HIP_TRY(launch_stage(X, t, n, ldx, mu, Xst, prec, true, true, s));
-    const bool was_timing = g_timing;
+    // timing of the library's own launches is off while candidates run; the
+    // events and that switch are restored on every way out
+    struct Guard {
+        bool was = g_timing;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Guard() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            g_timing = was;
+        }
+    } gd;
     g_timing = false;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventCreate(&gd.e0));
+    HIP_TRY(hipEventCreate(&gd.e1));
     float best_ms = 1e30f;
     const CallPlan *best_c = nullptr;
     for (const Call &c : cands) {
         float cand_ms = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
-            HIP_TRY(hipEventRecord(e0, s));
-            if ((st = run_orders(c, Xst, partial, outs, true, s))) break;
-            HIP_TRY(hipEventRecord(e1, s));
-            HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipEventRecord(gd.e0, s));
+            if ((st = run_orders(c, Xst, partial, outs, true, s, mp))) return st;
+            HIP_TRY(hipEventRecord(gd.e1, s));
+            HIP_TRY(hipEventSynchronize(gd.e1));
             float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            HIP_TRY(hipEventElapsedTime(&ms, gd.e0, gd.e1));
             if (rep > 0) cand_ms = std::min(cand_ms, ms);
         }
-        if (st) break;
         if (cand_ms < best_ms) {
             best_ms = cand_ms;
             best_c = c.c;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    g_timing = was_timing;
-    if (st) return st;
     HIP_TRY(hipStreamSynchronize(s));
     const int best_target = best_c->target;
     g_tuned[std::make_tuple(n, b, 2, d_max, (int)prec, t)] = Tuning{best_c->shape, best_target, best_c->bi};
@@ -1717,6 +1743,9 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
     if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
     for (int s = 0; s < n_sets; ++s)
         if (t_i[s] < 1) return fail(CUM_EINVAL, "t_i[%d] = %lld < 1", s, (long long)t_i[s]);
+    for (int d = 2; d <= d_max; ++d)
+        if (ipow64(b, d) > INT32_MAX)
+            return fail(CUM_EUNSUPPORTED, "blocks of b^d = %d^%d entries (2^31 or more) are not supported", b, d);
     std::lock_guard<std::mutex> lk(g_mu);
     std::unique_ptr<cum_batch, void (*)(cum_batch *)> p(new cum_batch, batch_free);
     p->nsets = n_sets;
@@ -1862,18 +1891,27 @@ cum_status cum_batch_timestamps(cum_batch *p, uint64_t *start, uint64_t *ticks, 
 cum_status cum_batch_autotune(cum_batch *p, const double *const *X_i, cum_tuning *best) {
     if (!p || !X_i) return fail(CUM_EINVAL, "NULL argument");
     std::vector<double *> kap((size_t)p->nsets * (p->d_max - 1));
-    // outputs of the trial runs go to a scratch buffer shared by all datasets
+    // outputs of the trial runs: a scratch buffer with every dataset's own
+    // slice (the recursion of a dataset reads its own lower orders)
     DevBuf scratch;
-    HIP_TRY(hipMalloc(&scratch.p, (size_t)p->kstride * sizeof(double)));
+    HIP_TRY(hipMalloc(&scratch.p, (size_t)p->nsets * p->kstride * sizeof(double)));
     for (int s = 0; s < p->nsets; ++s)
-        for (int d = 2; d <= p->d_max; ++d) kap[(size_t)s * (p->d_max - 1) + d - 2] = (double *)scratch.p + p->out_off[d - 2];
+        for (int d = 2; d <= p->d_max; ++d)
+            kap[(size_t)s * (p->d_max - 1) + d - 2] = (double *)scratch.p + (size_t)s * p->kstride + p->out_off[d - 2];
     const int shapes[] = {TS_1x1, TS_1x2};
     const int targets[] = {4096, 16384, 65536};
     float best_ms = 1e30f;
     int best_shape = p->shape, best_target = 16384, best_bi = p->bi;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    HIP_TRY(hipEventCreate(&ev.e0));
+    HIP_TRY(hipEventCreate(&ev.e1));
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     struct Cand {
         int bi, sh, tg;
     };
@@ -1907,8 +1945,6 @@ cum_status cum_batch_autotune(cum_batch *p, const double *const *X_i, cum_tuning
             best_bi = cd.bi;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     HIP_TRY(hipDeviceSynchronize());
     if (st) return st;
     std::lock_guard<std::mutex> lk(g_mu);

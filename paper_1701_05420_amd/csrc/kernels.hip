@@ -373,10 +373,19 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                                             const SetDev &sd, char *lds, int n, int wave) {
     typedef typename PT<PREC>::T T;
     constexpr int KT = PT<PREC>::KT, KTP = PT<PREC>::KTP;
-    constexpr bool BF = PREC >= P_BF16X2;
+    // Orders of HIGH_ACC64_MIN_D and above in the FP32-staged precisions: the
+    // operands are FP32 products of the staged samples as in the FP32 path,
+    // but each product of two operands is summed in FP64 on the matrix unit
+    // (exact product, FP64 accumulation).  At these orders the moments of
+    // heavy-tailed data are carried by a few extreme samples whose products
+    // nearly cancel, and an FP32 sum over a stage loses the digits the
+    // cumulant keeps.
+    constexpr bool HI = PREC != P_F64 && P + Q >= HIGH_ACC64_MIN_D;
+    constexpr bool ACC64 = PREC == P_F64 || HI;  // FP64 accumulators (FP64 16x16 output layout)
+    constexpr bool BF = PREC >= P_BF16X2 && !HI;
     constexpr int NS = (PREC == P_BF16X3) ? 3 : 2;  // split terms (BF16 paths)
     // samples per step group: lane group g (= lane / 16) holds VEC consecutive samples
-    constexpr int VEC = (PREC == P_F64) ? 2 : (PREC == P_F32 ? 4 : 8);
+    constexpr int VEC = (PREC == P_F64) ? 2 : (PREC == P_F32 || HI ? 4 : 8);
     constexpr int STEP = 4 * VEC;
     const int tid = threadIdx.x, lane = tid & 63;
     const int stage_bytes = (n + 1) * KTP * (int)sizeof(T);
@@ -493,9 +502,9 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                                 if (all || (vmask >> (j * 4 + h * 2 + g) & 1u)) {
 #pragma unroll
                                     for (int u = 0; u < VEC; ++u) {
-                                        if constexpr (PREC == P_F64)
+                                        if constexpr (ACC64)
                                             acc64[j][h][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                                A[h][u], B[j][g][u], acc64[j][h][g], 0, 0, 0);
+                                                (double)A[h][u], (double)B[j][g][u], acc64[j][h][g], 0, 0, 0);
                                         else
                                             acc[j][h][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                                                 A[h][u], B[j][g][u], acc[j][h][g], 0, 0, 0);
@@ -572,7 +581,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
         // not storing, the sub-blocks without stored entries) to keep its
         // registers down; the others have a test-free copy for full tasks and
         // a tested one for tasks on the edge of the stored region.
-        if constexpr (PREC == P_BF16X3) {
+        if constexpr (PREC == P_BF16X3 && !HI) {
             if (vmask) stage(std::true_type());
         } else {
             if (vmask == (1u << (4 * WN)) - 1u)
@@ -582,7 +591,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
         }
         wait_dma();
         __syncthreads();
-        if constexpr (PREC != P_F64) {
+        if constexpr (!ACC64) {
             // Carry the FP32 sums into FP64.  The leading products of the FP32
             // and three-term paths are carried after every stage.  The
             // three-term path's small products (2^-8 of the leading ones and
@@ -636,10 +645,10 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     // 16 x 16 accumulator layouts: FP64 rows 4q + lane/16, FP32 rows 4*(lane/16) + q
-                    const int r = rbase + 16 * h + (PREC == P_F64 ? 4 * q + (lane >> 4) : 4 * (lane >> 4) + q);
+                    const int r = rbase + 16 * h + (ACC64 ? 4 * q + (lane >> 4) : 4 * (lane >> 4) + q);
                     const Feat fr = od.rows[r];
                     if (fr.blk <= fc.blk) {
-                        const double val = (PREC == P_F64) ? acc64[j][h][g][q] : dacc[j][h][g][q];
+                        const double val = ACC64 ? acc64[j][h][g][q] : dacc[j][h][g][q];
                         dst[fr.addr + fc.addr + od.H[(int64_t)fr.blk * od.nbar + fc.blk]] = val;
                     }
                 }

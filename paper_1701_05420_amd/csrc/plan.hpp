@@ -134,6 +134,9 @@ struct RedOrder {
 // moment-cumulant relation (when the central moments of lower orders are
 // kept); lower orders keep the partition recursion.
 constexpr int FIRST_POSITION_MIN_D = 7;
+// Smallest order whose contraction sums in FP64 in every precision (the
+// FP32-staged ones form FP32 operands and accumulate their products in FP64).
+constexpr int HIGH_ACC64_MIN_D = 7;
 constexpr int RED_LDS_MAX = 6144;  // doubles of lower-order sub-blocks staged per block (48 KiB)
 
 struct SetRed {

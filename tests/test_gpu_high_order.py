@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import workloads
+from errmeasure import e_d
 
 pytestmark = pytest.mark.gpu
 
@@ -59,9 +60,8 @@ def test_high_order_float_fp64(dev, orc):
 def test_high_order_float_sampled(dev, orc, prec, n, b, dmax):
     """Orders 9 and 10 on float data, every precision: the oracle's per-entry
     route (all set partitions of the positions, FP64) at 64 random multi-
-    indices and every pure diagonal, read through the block storage.  The
-    error is taken relative to max(max|oracle|, s_d), s_d = max_i mean_l
-    |x~_li|^d, which bounds every entry of M_d."""
+    indices and every pure diagonal, read through the block storage, with
+    the error e_d relative to the largest sampled oracle entry."""
     torch, pc = dev
     TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
     X = workloads.laplace_mix(t=2000, n=n, seed=90 + n)
@@ -74,8 +74,7 @@ def test_high_order_float_sampled(dev, orc, prec, n, b, dmax):
         idx = np.concatenate([rng.integers(0, n, size=(64, d)), np.repeat(np.arange(n)[:, None], d, axis=1)])
         want = orc.cumulant_at(Xc, idx.astype(np.int32))
         got = K[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
-        s_d = (np.abs(Xc) ** d).mean(axis=0).max()
-        e = np.abs(got - want).max() / max(np.abs(want).max(), s_d)
+        e = e_d(got, want, d)
         say(f"  e_{d} = {e:.3e}")
         assert e <= TOL[prec], (d, e)
 
@@ -97,7 +96,43 @@ def test_high_order_many_blocks(dev, orc):
         idx = np.concatenate([rng.integers(0, n, size=(64, d)), np.repeat(np.arange(n)[:, None], d, axis=1)])
         want = orc.cumulant_at(Xc, idx.astype(np.int32))
         got = K[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
-        s_d = (np.abs(Xc) ** d).mean(axis=0).max()
-        e = np.abs(got - want).max() / max(np.abs(want).max(), s_d)
+        e = e_d(got, want, d)
+        say(f"  e_{d} = {e:.3e}")
+        assert e <= 1e-6, (d, e)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x2", "bf16x3"])
+def test_high_order_float_mixed_dense(dev, orc, prec):
+    """Orders 7 and 8 in the FP32-staged precisions on float data, every
+    stored entry against the dense oracle: these orders accumulate their
+    products in FP64, so the 1e-6 bound holds for every such precision."""
+    torch, pc = dev
+    n, b, dmax, t = 4, 3, 8, 1500
+    X = workloads.laplace_mix(t=t, n=n, seed=8)
+    _, OK = orc.cumulants_dense(X, dmax)
+    _, K = pc.cumulants(torch.from_numpy(X).cuda(), dmax, b, prec)
+    torch.cuda.synchronize()
+    tol = {2: 5e-5, 3: 5e-5, 4: 5e-5, 5: 5e-5, 6: 5e-5} if prec == "bf16x2" else {}
+    for d in range(2, dmax + 1):
+        e = e_d(K[d].cpu().numpy(), orc.fold(OK[d], b), d)
+        say(f"  {prec} e_{d} = {e:.3e}")
+        assert e <= tol.get(d, 1e-6), (d, e)
+
+
+def test_high_order_benchmark_case(dev, orc):
+    """The measured high-order case (n = 16, b = 2, d <= 8, t = 2e4, FP32):
+    the two top orders at 64 random entries and every pure diagonal."""
+    torch, pc = dev
+    n, b, dmax, t = 16, 2, 8, 20_000
+    X = workloads.laplace_mix(t=t, n=n, seed=1701006)
+    _, K = pc.cumulants(torch.from_numpy(X).cuda(), dmax, b, "f32")
+    torch.cuda.synchronize()
+    Xc = X - X.mean(axis=0)
+    rng = np.random.default_rng(dmax)
+    for d in (dmax - 1, dmax):
+        idx = np.concatenate([rng.integers(0, n, size=(64, d)), np.repeat(np.arange(n)[:, None], d, axis=1)])
+        want = orc.cumulant_at(Xc, idx.astype(np.int32))
+        got = K[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
+        e = e_d(got, want, d)
         say(f"  e_{d} = {e:.3e}")
         assert e <= 1e-6, (d, e)

@@ -290,3 +290,33 @@ def test_graph_capture_replays(dev, orc, prec):
     _, OK = orc.cumulants_dense(X, dmax)
     for d in out:
         assert rel(out[d].cpu().numpy(), orc.fold(OK[d], b)) <= TOL[prec]
+
+
+def test_side_stream_without_workspace(dev, orc):
+    """Calls on a stream other than the current one, with no workspace or
+    outputs passed in: the binding allocates them for that stream, so work
+    queued meanwhile on the current stream cannot reuse them while the
+    call's kernels run.  Same bits as a call on the current stream."""
+    torch, pc = dev
+    n, b, dmax, t = 12, 3, 4, 20_000
+    X = workloads.t_gamma_mix(t=t, n=n, seed=31)
+    Xd = torch.from_numpy(X).cuda()
+    _, ref = pc.cumulants(Xd, dmax, b, "f32")
+    mref = pc.moment_blocks(pc.center(Xd, "f32")[1], 3, b)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    for rep in range(3):
+        _, K = pc.cumulants(Xd, dmax, b, "f32", stream=s)
+        mean_c, Xc = pc.center(Xd, "f32", stream=s)
+        M = pc.moment_blocks(Xc, 3, b, stream=s)
+        # traffic on the current stream that would reuse freed blocks at once
+        junk = [torch.full((1 << 20,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(8)]
+        del junk
+        torch.cuda.synchronize()
+        for d in ref:
+            assert torch.equal(K[d], ref[d]), (rep, d)
+        assert torch.equal(M, mref), rep
+    _, OK = orc.cumulants_dense(X, dmax)
+    for d in ref:
+        assert rel(ref[d].cpu().numpy(), orc.fold(OK[d], b)) <= TOL["f32"]

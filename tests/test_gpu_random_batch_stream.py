@@ -3,15 +3,16 @@ dense CPU oracle: variables, block size, order, precision, dataset count and
 sizes (t_i = 1 included), and random add / remove sequences over a window.
 Each case prints its configuration before it runs.
 
-Errors are taken relative to max(max|oracle|, s_d), s_d = max_i mean_l
-|x~_li|^d, which bounds every entry of M_d (Hoelder): with two samples the odd
-cumulants vanish in exact arithmetic and the oracle holds only rounding."""
+Errors are e_d, relative to the largest oracle entry of each order (with two
+samples the odd cumulants vanish in exact arithmetic and are scaled by the
+moments instead: tests/errmeasure.py)."""
 import sys
 
 import numpy as np
 import pytest
 
 import workloads
+from errmeasure import e_d
 
 pytestmark = pytest.mark.gpu
 
@@ -35,8 +36,8 @@ def say(*a):
 
 
 def check(orc, X, mean, K, d_max, b, tol, shift=None):
-    """Parity of one window.  A stream sums about `shift`: its roundings scale
-    with the moments about the shift, so those bound the error there too."""
+    """Parity of one window (a stream sums about `shift`, which these tests
+    keep near the data's mean)."""
     om, OK = orc.cumulants_dense(X, d_max)
     assert np.abs(mean - om).max() <= 1e-13 * max(1.0, np.abs(X).max())
     for d in range(2, d_max + 1):
@@ -45,10 +46,8 @@ def check(orc, X, mean, K, d_max, b, tol, shift=None):
         if len(X) == 1 and shift is None:
             assert not np.any(got), d
             continue
-        s_d = (np.abs(X - om) ** d).mean(axis=0).max()
-        if shift is not None:
-            s_d = max(s_d, (np.abs(X - shift) ** d).mean(axis=0).max())
-        e = np.abs(got - want).max() / max(np.abs(want).max(), s_d)
+        e = e_d(got, want, d, X - om)
+        say(f"  e_{d} = {e:.3e}")
         assert e <= tol, (d, e)
 
 

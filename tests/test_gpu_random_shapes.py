@@ -3,17 +3,16 @@ block size (ragged or not), order, sample count, precision and every tuned
 knob (inner block size, task shape, work-item target).  Each case prints its
 configuration before it runs.
 
-The error of order d is taken relative to max(max|oracle|, s_d), where
-s_d = max_i mean_l |x~_li|^d bounds every entry of the moment tensor M_d
-(Hoelder).  The moments carry the rounding, and with t = 2 the odd cumulants
-vanish in exact arithmetic: there the oracle holds only rounding noise and
-max|oracle| alone is no scale."""
+The error of order d is e_d, relative to the largest oracle entry of that
+order (with t = 2 the odd cumulants vanish in exact arithmetic and are
+scaled by the moments instead: tests/errmeasure.py)."""
 import sys
 
 import numpy as np
 import pytest
 
 import workloads
+from errmeasure import e_d
 
 pytestmark = pytest.mark.gpu
 
@@ -70,6 +69,6 @@ def test_random_configuration(dev, orc, n, b, d_max, t, prec, inner, shape, targ
         if t == 1:
             assert not np.any(got), d
             continue
-        s_d = (np.abs(X - om) ** d).mean(axis=0).max()
-        e = np.abs(got - want).max() / max(np.abs(want).max(), s_d)
+        e = e_d(got, want, d, X - om)
+        print(f"  e_{d} = {e:.3e}", file=sys.stderr, flush=True)
         assert e <= TOL[prec], (d, e)

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import workloads
+from errmeasure import e_d
 
 pytestmark = pytest.mark.gpu
 
@@ -208,8 +209,7 @@ def test_stream_high_order_window(dev, orc, prec):
     tol = 1e-10 if prec == "f64" else 1e-6
     for d in range(2, dmax + 1):
         want = orc.fold(OK[d], b)
-        s_d = (np.abs(Xw - om) ** d).mean(axis=0).max()
-        e = np.abs(K[d].cpu().numpy() - want).max() / max(np.abs(want).max(), s_d)
+        e = e_d(K[d].cpu().numpy(), want, d, Xw - om)
         say(f"  e_{d} = {e:.3e}")
         assert e <= tol, (d, e)
     st.close()

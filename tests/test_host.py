@@ -228,3 +228,21 @@ def test_workspace_holds_lower_moments_from_order_7(pc):
     t, n, b = 20_000, 8, 2
     lower = sum(pc.layout(n, m, b)["elems"] * 8 for m in range(2, 6))
     assert pc.workspace_size(t, n, 7, b, "f32") >= pc.workspace_size(t, n, 6, b, "f32") + lower
+
+
+def test_blocks_beyond_32_bit_entries_are_refused(pc):
+    """b^d is checked without wrapping: 97^10 and 112^10 exceed 64 bits and
+    wrapped to negative values in a plain product."""
+    P = ctypes.c_void_p(0x1000)
+    for n, b in [(100, 97), (112, 112), (112, 84)]:
+        L = pc.Layout()
+        assert _raw(pc, "cum_layout_query", n, 10, b, ctypes.byref(L)) == -4
+        sz = ctypes.c_size_t()
+        assert _raw(pc, "cum_workspace_size", 1000, n, 10, b, 1, ctypes.byref(sz)) == -4
+        assert _raw(pc, "cum_moment_blocks", P, 1, 1000, n, 10, b, P, P, 1 << 40, None) == -4
+        h = ctypes.c_void_p()
+        assert _raw(pc, "cum_stream_create", n, 10, b, 1, None, ctypes.byref(h)) == -4
+        ts = (ctypes.c_int64 * 2)(100, 200)
+        assert _raw(pc, "cum_batch_create", 2, ts, n, 10, b, 1, ctypes.byref(h)) == -4
+    # within 32 bits the layout is reported exactly
+    assert pc.layout(100, 4, 97)["block_elems"] == 97 ** 4
