@@ -183,6 +183,70 @@ def cpu_baseline(orc, X, n, d_max, b, pc, target_s):
             "single_thread": {"value": v1, "sample": f"first {ts1} samples, {dt1:.1f} s"}}
 
 
+def _oracle_seconds(orc, X, d_max):
+    t0 = time.perf_counter()
+    orc.cumulants_dense(X, d_max)
+    return time.perf_counter() - t0
+
+
+def _oracle_extrapolated(orc, pc, X, n, d_max, b, n_sub, slices):
+    """Dense oracle time of the full workload, extrapolated: the oracle on the
+    first n_sub variables and two leading sample slices gives a + c * ts
+    (a: the sample-independent recursion, c: the moment sums per sample);
+    the full time is (a + c * t) * (n / n_sub)^d_max (the top order's n^d
+    entries dominate both parts)."""
+    t = len(X)
+    times = [_oracle_seconds(orc, X[:ts, :n_sub], d_max) for ts in slices]
+    c = (times[1] - times[0]) / (slices[1] - slices[0])
+    a = max(times[0] - c * slices[0], 0.0)
+    full = (a + c * t) * (n / n_sub) ** d_max
+    return {"mode": "extrapolated",
+            "sample": f"dense oracle on the first {n_sub} of {n} variables and the first {slices[0]} and "
+                      f"{slices[1]} samples ({times[0]:.1f} s, {times[1]:.1f} s); full time (a + c t) "
+                      f"(n / {n_sub})^{d_max}",
+            "measured_seconds": times, "seconds_full": full,
+            "tflops": alg_flops(pc, t, n, d_max, b) / full / 1e12}
+
+
+def cpu_oracle_configs(orc, pc):
+    """The dense FP64 oracle (every n^d entry, all host threads) on the other
+    workloads, as a stated CPU baseline: the n = 16 workload in full, the
+    first 16 datasets of the 512-dataset batch in full, and the n = 24 (d <= 6)
+    and n = 64 (d <= 5) workloads extrapolated from timed slices."""
+    import workloads
+
+    out = {"cores": orc.max_threads(), "cpu_model": cpu_model()}
+    name = "t-wishart-n16-t5000"
+    w = workloads.WORKLOADS[name]
+    X = workloads.generate(name)
+    dt = _oracle_seconds(orc, X, w["d_max"])
+    cores = orc.max_threads()
+    orc.set_threads(1)
+    try:
+        dt1 = _oracle_seconds(orc, X, w["d_max"])
+    finally:
+        orc.set_threads(cores)
+    fl = alg_flops(pc, w["t"], w["n"], w["d_max"], w["b"])
+    out[name] = {"mode": "full dense", "seconds": dt, "tflops": fl / dt / 1e12,
+                 "single_thread": {"seconds": dt1, "tflops": fl / dt1 / 1e12}}
+    log(f"  oracle {name}: {dt:.2f} s ({dt1:.2f} s on one thread)")
+    name = "batch512-t-corr-n32"
+    w = workloads.WORKLOADS[name]
+    Xs = workloads.generate(name)[:16]
+    dt = sum(_oracle_seconds(orc, X, w["d_max"]) for X in Xs)
+    fl = sum(alg_flops(pc, len(X), w["n"], w["d_max"], w["b"]) for X in Xs)
+    out[name] = {"mode": "full dense on the first 16 of the 512 datasets", "seconds": dt,
+                 "datasets_per_s": 16 / dt, "tflops": fl / dt / 1e12,
+                 "samples": int(sum(len(X) for X in Xs))}
+    log(f"  oracle {name} (16 datasets): {dt:.2f} s")
+    for name, n_sub, slices in [("laplace-mix-n24-t200000", 16, (16, 48)), ("ar1-garch-n64-t50000", 32, (64, 192))]:
+        w = workloads.WORKLOADS[name]
+        X = workloads.generate(name)
+        out[name] = _oracle_extrapolated(orc, pc, X, w["n"], w["d_max"], w["b"], n_sub, slices)
+        log(f"  oracle {name}: {out[name]['seconds_full']:.0f} s extrapolated")
+    return out
+
+
 def bench_batched(torch, pc, prec, steps, warmup, tune):
     """The 512-dataset workload: one graph replay per step vs one
     cum_cumulants call per dataset; datasets/s and per-dataset latency."""
@@ -195,6 +259,7 @@ def bench_batched(torch, pc, prec, steps, warmup, tune):
     ts = [len(X) for X in Xs]
     Xd = [torch.from_numpy(X).cuda() for X in Xs]
     flops = sum(alg_flops(pc, t, n, d_max, b) for t in ts)
+    uflops = sum(alg_flops(pc, t, n, d_max, 1) for t in ts)
     batch = pc.Batch(ts, n, d_max, b, prec)
     tuned = batch.autotune(Xd) if tune else None
     out = [{d: torch.empty(pc.layout(n, d, b)["elems"], dtype=torch.float64, device="cuda")
@@ -229,6 +294,7 @@ def bench_batched(torch, pc, prec, steps, warmup, tune):
     seq_lat = np.array([ev0.elapsed_time(e) for e in evs])
     return {"workload": name, "n_sets": len(ts), "prec": prec, "t_total": int(sum(ts)),
             "ms_per_batch": ms, "datasets_per_s": len(ts) / ms * 1e3, "eff_tflops": flops / (ms * 1e-3) / 1e12,
+            "tflops_unique": uflops / (ms * 1e-3) / 1e12,
             "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
             "per_dataset_calls": {"ms_total": seq_ms, "datasets_per_s": len(ts) / seq_ms * 1e3,
                                   "latency_ms_p50": float(np.percentile(seq_lat, 50)),
@@ -237,10 +303,14 @@ def bench_batched(torch, pc, prec, steps, warmup, tune):
 
 
 def bench_workloads(torch, pc, orc, steps, tune):
-    """The higher-order workloads (d_max = 6 and 5), FP32 and FP64 paths:
-    step time, effective and moment-kernel throughput, and e_d per order
-    against the oracle on sampled entries (random positions, every pure
-    diagonal, and entries of blocks with repeated block indices)."""
+    """The higher-order workloads (d_max = 6 and 5) in every precision (FP32,
+    FP64 and the two- and three-term BF16 splits): step time, effective
+    throughput (the block method's FLOP, 2 t sum_d stored_d) and the same
+    time against the distinct-tuple lower bound (2 t sum_d C(n+d-1, d)),
+    moment-kernel throughput and matrix-unit fraction (issued products:
+    4 or 6 per FMA for the BF16 splits), and e_d per order against the
+    oracle on about 300 sampled entries per order (random positions, every
+    pure diagonal, and copies in blocks with repeated block indices)."""
     import workloads
 
     out = {}
@@ -251,22 +321,29 @@ def bench_workloads(torch, pc, orc, steps, tune):
         X = workloads.generate(name)
         Xd = torch.from_numpy(X).cuda()
         flops = alg_flops(pc, t, n, d_max, b)
+        uflops = alg_flops(pc, t, n, d_max, 1)
         res, kap = {}, {}
-        for p in ["f32", "f64"]:
+        for p in ["f32", "f64", "bf16x3", "bf16x2"]:
             wall, kinds, o, tuned, pct = time_path(torch, pc, Xd, d_max, b, p, steps, 2, tune)
             cfg = pc.get_tuning(t, n, d_max, b, p)
             kflops = alg_flops(pc, t, n, d_max, cfg["inner_b"])
             per_launch = kinds["moment"][0] / max(kinds["moment"][1], 1)
-            res[p] = {"ms_per_step": wall * 1e3, "tflops": flops / wall / 1e12, "ms_per_step_pct": pct,
-                      "moment_tflops": kflops / (per_launch * 1e-3) / 1e12,
-                      "mfma_frac": kflops / (per_launch * 1e-3) / 1e12 / PEAK[p], "config": cfg,
+            mt = kflops / (per_launch * 1e-3) / 1e12
+            res[p] = {"ms_per_step": wall * 1e3, "tflops": flops / wall / 1e12,
+                      "tflops_unique": uflops / wall / 1e12, "ms_per_step_pct": pct,
+                      "moment_ms_per_launch": per_launch, "moment_tflops": mt,
+                      "mfma_frac": mt * PRODUCTS[p] / PEAK[p], "config": cfg,
+                      "kernel_ms": {k: v[0] / steps for k, v in kinds.items() if v[1]},
                       "finalisation": finalisation_record(pc, kinds, steps, t, n, d_max, b, p)}
             kap[p] = {d: o[d].cpu().numpy() for d in o}
-            log(f"  {p}: {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s")
-        errs = sampled_errors(orc, pc, X, kap, n, d_max, b, count=40, seed=11)
+            log(f"  {p}: {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s "
+                f"({uflops / wall / 1e12:.2f} on distinct tuples); moment kernel {mt:.1f} TFLOP/s")
+        errs = sampled_errors(orc, pc, X, kap, n, d_max, b, count=300, seed=11)
         for p in res:
             res[p]["rel_err"] = {str(d): errs[d][p] for d in errs}
-        out[name] = {"n": n, "b": b, "d_max": d_max, "t": t, "alg_flop_per_step": flops, "paths": res}
+            log(f"  {p}: e_d " + " ".join(f"{d}:{errs[d][p]:.2e}" for d in errs))
+        out[name] = {"n": n, "b": b, "d_max": d_max, "t": t, "alg_flop_per_step": flops,
+                     "unique_flop_per_step": uflops, "paths": res}
     return out
 
 
@@ -295,8 +372,10 @@ def bench_high_orders(torch, pc, orc, steps):
             want = orc.cumulant_at(Xc, idx.astype(np.int32))
             got = o[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
             errs[str(d)] = float(np.abs(got - want).max() / np.abs(want).max())
+        uflops = alg_flops(pc, t, n, d_max, 1)
         out[name] = {"n": n, "b": b, "d_max": d_max, "t": t, "prec": "f32", "ms_per_step": wall * 1e3,
-                     "ms_per_step_pct": pct, "tflops": flops / wall / 1e12, "kernel_ms": ms,
+                     "ms_per_step_pct": pct, "tflops": flops / wall / 1e12,
+                     "tflops_unique": uflops / wall / 1e12, "kernel_ms": ms,
                      "stored_entries": pc.plan_info(t, n, d_max, b, "f32")["stored_entries"],
                      "rel_err_sampled": errs}
         log(f"  {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s; kernels {ms}; e {errs}")
@@ -557,6 +636,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(orc, X, n, d_max, b, pc, args.cpu_seconds)
+        line["cpu_baseline"]["other_workloads"] = cpu_oracle_configs(orc, pc)
     print(json.dumps(line), flush=True)
 
 
