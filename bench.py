@@ -351,8 +351,9 @@ def bench_high_orders(torch, pc, orc, steps):
     """Orders to 8 and 10 (the recursion's partition tables grow to 715 and
     17722 terms per entry): step time, effective throughput, the split of
     kernel time between the contraction and the finalisation, and e_d of the
-    top orders against the oracle's per-entry route (FP32 path, planner
-    defaults)."""
+    top orders against the oracle's per-entry route (FP32 requested, planner
+    defaults; from d_max = 7 on the library stages and contracts in FP64,
+    since FP32-rounded samples alone put e_8 above 1e-6)."""
     import workloads
 
     out = {}
@@ -373,7 +374,7 @@ def bench_high_orders(torch, pc, orc, steps):
             got = o[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
             errs[str(d)] = float(np.abs(got - want).max() / np.abs(want).max())
         uflops = alg_flops(pc, t, n, d_max, 1)
-        out[name] = {"n": n, "b": b, "d_max": d_max, "t": t, "prec": "f32", "ms_per_step": wall * 1e3,
+        out[name] = {"n": n, "b": b, "d_max": d_max, "t": t, "prec": "f32", "contraction_prec": "f64", "ms_per_step": wall * 1e3,
                      "ms_per_step_pct": pct, "tflops": flops / wall / 1e12,
                      "tflops_unique": uflops / wall / 1e12, "kernel_ms": ms,
                      "stored_entries": pc.plan_info(t, n, d_max, b, "f32")["stored_entries"],

@@ -72,7 +72,10 @@ typedef enum {
 
 /* Arithmetic of the moment contraction (the sum over samples of Alg. 1).
  * Centring, the cross-chunk reduction and the cumulant recursion are FP64 in
- * every mode. */
+ * every mode.  Calls that centre their own data (cum_cumulants, batches,
+ * streams) with d_max >= 7 stage and contract in FP64 whatever prec says:
+ * rounding the centred samples to FP32 alone leaves cumulants of orders 7
+ * and above on heavy-tailed data more than 1e-6 (relative) off. */
 typedef enum {
     CUM_F64 = 0,    /* FP64 data, FP64 matrix-core products and sums            */
     CUM_F32 = 1,    /* FP32 data, FP32 matrix-core products, FP32 sums over at  */
@@ -80,8 +83,13 @@ typedef enum {
     CUM_BF16X2 = 2, /* FP32 data; each half-product split into two BF16 terms, */
                     /* all 4 cross products on BF16 matrix cores, FP32 sums    */
                     /* over at most 64 samples, then FP64                       */
-    CUM_BF16X3 = 3  /* as BF16X2 with a three-term split and the 6 cross       */
+    CUM_BF16X3 = 3, /* as BF16X2 with a three-term split and the 6 cross       */
                     /* products of combined weight >= 2^-16                     */
+    /* Not precisions: these give the enum the range of int32_t, so that an
+     * unknown value is a valid cum_prec object that the library rejects with
+     * CUM_EUNSUPPORTED (without them, reading one is undefined in C++). */
+    CUM_PREC_RANGE_LO_ = -2147483647 - 1,
+    CUM_PREC_RANGE_HI_ = 2147483647
 } cum_prec;
 
 /* Block layout of one order (Section 2.1). */
@@ -135,7 +143,8 @@ cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, in
  *   mean   n FP64 out (the first cumulant), or NULL
  *   kappa  (host) array of d_max-1 device pointers; kappa[d-2] receives c_d
  *          in block storage (cum_layout(n, d, b).elems FP64 each)
- * The data are centred in FP64; only the moment contraction runs in prec.
+ * The data are centred in FP64; only the moment contraction runs in prec
+ * (in FP64 when d_max >= 7, see cum_prec).
  * Requires t >= 1, 1 <= b <= n, 2 <= d_max <= CUM_MAX_ORDER.  The first call
  * of a configuration builds its tables (device allocations); later calls
  * allocate nothing and enqueue only kernels, so they may be captured in a

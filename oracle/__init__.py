@@ -24,21 +24,28 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cumoracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIBRARY names another build of the oracle (the sanitizer build)
+_BUILD_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_PATH = os.environ.get("ORACLE_LIBRARY") or _BUILD_PATH
+_SAN_PATH = os.path.join(_HERE, "liboracle.asan.so")
 _lib = None
 
 MAXD = 10
 
 
-def build(force: bool = False) -> str:
-    """Compile the C oracle in place (gcc, OpenMP, no FP contraction)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp"
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the C oracle in place (gcc, OpenMP, no FP contraction); with
+    sanitize, a separate build under AddressSanitizer and
+    UndefinedBehaviorSanitizer."""
+    path = _SAN_PATH if sanitize else _BUILD_PATH
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp"
+        san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
         subprocess.check_call(
             ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
-             "-Wall", "-o", tmp, _SRC])
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+             "-Wall", *(san if sanitize else []), "-o", tmp, _SRC])
+        os.replace(tmp, path)
+    return path
 
 
 def _load():

@@ -17,7 +17,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcumulants.so")
+# CUM_LIBRARY names another build of the same library (the host-sanitizer
+# build, for instance)
+LIB_PATH = os.environ.get("CUM_LIBRARY") or os.path.join(_HERE, "libcumulants.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1701_05420_amd/build.py` "

@@ -137,6 +137,9 @@ constexpr int FIRST_POSITION_MIN_D = 7;
 // Smallest order whose contraction sums in FP64 in every precision (the
 // FP32-staged ones form FP32 operands and accumulate their products in FP64).
 constexpr int HIGH_ACC64_MIN_D = 7;
+// Smallest d_max at which a call that centres its own data stages it in FP64
+// and runs its whole contraction in FP64, whatever precision was asked for.
+constexpr int HIGH_F64_MIN_D = 7;
 constexpr int RED_LDS_MAX = 6144;  // doubles of lower-order sub-blocks staged per block (48 KiB)
 
 struct SetRed {

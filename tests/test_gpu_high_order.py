@@ -1,6 +1,8 @@
 """Orders 7..10 (the paper states its method is practical up to the tenth
-order): exact on small-integer data for every path, and FP64 against the
-dense oracle on floating-point data."""
+order): exact on small-integer data for every path, and against the oracle
+on floating-point data.  Calls with d_max >= 7 stage and contract in FP64
+in every precision (FP32-rounded samples alone put the cumulants of order 8
+more than 1e-6 off), so every precision is held to the FP64 target there."""
 import sys
 
 import numpy as np
@@ -61,9 +63,9 @@ def test_high_order_float_sampled(dev, orc, prec, n, b, dmax):
     """Orders 9 and 10 on float data, every precision: the oracle's per-entry
     route (all set partitions of the positions, FP64) at 64 random multi-
     indices and every pure diagonal, read through the block storage, with
-    the error e_d relative to the largest sampled oracle entry."""
+    the error e_d relative to the largest sampled oracle entry, held to the
+    FP64 target in every precision."""
     torch, pc = dev
-    TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
     X = workloads.laplace_mix(t=2000, n=n, seed=90 + n)
     say(f"high order sampled prec={prec} n={n} b={b} dmax={dmax}")
     mean, K = pc.cumulants(torch.from_numpy(X).cuda(), dmax, b, prec)
@@ -76,14 +78,14 @@ def test_high_order_float_sampled(dev, orc, prec, n, b, dmax):
         got = K[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
         e = e_d(got, want, d)
         say(f"  e_{d} = {e:.3e}")
-        assert e <= TOL[prec], (d, e)
+        assert e <= 1e-10, (d, e)
 
 
 def test_high_order_many_blocks(dev, orc):
     """n = 16, b = 2, d <= 10: order 10 has 19448 blocks of 1024 entries, cut
     into four work-groups each, more than one launch row of work-groups
-    holds (65535), so work-groups take several slices in turn.  FP32 path,
-    sampled against the oracle's per-entry route."""
+    holds (65535), so work-groups take several slices in turn.  FP32 asked
+    for (FP64 used), sampled against the oracle's per-entry route."""
     torch, pc = dev
     n, b, dmax = 16, 2, 10
     X = workloads.laplace_mix(t=2000, n=n, seed=77)
@@ -98,30 +100,30 @@ def test_high_order_many_blocks(dev, orc):
         got = K[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
         e = e_d(got, want, d)
         say(f"  e_{d} = {e:.3e}")
-        assert e <= 1e-6, (d, e)
+        assert e <= 1e-10, (d, e)
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x2", "bf16x3"])
 def test_high_order_float_mixed_dense(dev, orc, prec):
-    """Orders 7 and 8 in the FP32-staged precisions on float data, every
-    stored entry against the dense oracle: these orders accumulate their
-    products in FP64, so the 1e-6 bound holds for every such precision."""
+    """d_max = 8 with the FP32-staged precisions asked for, on float data,
+    every stored entry of every order against the dense oracle: the call
+    runs in FP64, so the FP64 target holds for every order."""
     torch, pc = dev
     n, b, dmax, t = 4, 3, 8, 1500
     X = workloads.laplace_mix(t=t, n=n, seed=8)
     _, OK = orc.cumulants_dense(X, dmax)
     _, K = pc.cumulants(torch.from_numpy(X).cuda(), dmax, b, prec)
     torch.cuda.synchronize()
-    tol = {2: 5e-5, 3: 5e-5, 4: 5e-5, 5: 5e-5, 6: 5e-5} if prec == "bf16x2" else {}
     for d in range(2, dmax + 1):
         e = e_d(K[d].cpu().numpy(), orc.fold(OK[d], b), d)
         say(f"  {prec} e_{d} = {e:.3e}")
-        assert e <= tol.get(d, 1e-6), (d, e)
+        assert e <= 1e-10, (d, e)
 
 
 def test_high_order_benchmark_case(dev, orc):
-    """The measured high-order case (n = 16, b = 2, d <= 8, t = 2e4, FP32):
-    the two top orders at 64 random entries and every pure diagonal."""
+    """The measured high-order case (n = 16, b = 2, d <= 8, t = 2e4, FP32
+    asked for, FP64 used): the two top orders at 64 random entries and every
+    pure diagonal."""
     torch, pc = dev
     n, b, dmax, t = 16, 2, 8, 20_000
     X = workloads.laplace_mix(t=t, n=n, seed=1701006)
@@ -135,4 +137,4 @@ def test_high_order_benchmark_case(dev, orc):
         got = K[d].cpu().numpy()[[pc.stored_offset(n, d, b, list(ix)) for ix in idx]]
         e = e_d(got, want, d)
         say(f"  e_{d} = {e:.3e}")
-        assert e <= 1e-6, (d, e)
+        assert e <= 1e-10, (d, e)

@@ -5,14 +5,16 @@ Each case prints its configuration before it runs.
 
 Errors are e_d, relative to the largest oracle entry of each order (with two
 samples the odd cumulants vanish in exact arithmetic and are scaled by the
-moments instead: tests/errmeasure.py)."""
+moments instead), held to the path's target; the FP32-staged paths on fewer
+than 500 samples are held to the target times the cancellation
+max|M_d| / max|kappa_d| (tests/errmeasure.py)."""
 import sys
 
 import numpy as np
 import pytest
 
 import workloads
-from errmeasure import e_d
+from errmeasure import bound, e_d
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +37,7 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def check(orc, X, mean, K, d_max, b, tol, shift=None):
+def check(orc, X, mean, K, d_max, b, tol, prec, shift=None):
     """Parity of one window (a stream sums about `shift`, which these tests
     keep near the data's mean)."""
     om, OK = orc.cumulants_dense(X, d_max)
@@ -47,8 +49,9 @@ def check(orc, X, mean, K, d_max, b, tol, shift=None):
             assert not np.any(got), d
             continue
         e = e_d(got, want, d, X - om)
-        say(f"  e_{d} = {e:.3e}")
-        assert e <= tol, (d, e)
+        tl = bound(tol, prec, len(X), orc, X - om, OK[d], d)
+        say(f"  e_{d} = {e:.3e} (tolerance {tl:.3e})")
+        assert e <= tl, (d, e, tl)
 
 
 def batch_cases(count=10, seed=17010):
@@ -76,7 +79,7 @@ def test_random_batch(dev, orc, n, b, d_max, prec, ts, seed):
         means, K = batch.run([torch.from_numpy(X).cuda() for X in Xs])
         torch.cuda.synchronize()
         for s, X in enumerate(Xs):
-            check(orc, X, means[s].cpu().numpy(), {d: K[s][d].cpu().numpy() for d in K[s]}, d_max, b, TOL[prec])
+            check(orc, X, means[s].cpu().numpy(), {d: K[s][d].cpu().numpy() for d in K[s]}, d_max, b, TOL[prec], prec)
     finally:
         batch.close()
 
@@ -123,6 +126,6 @@ def test_random_stream_sequence(dev, orc, n, b, d_max, prec, method, seed):
                 assert st.count() == len(Xw)
                 mean, K = st.cumulants(method=method)
                 torch.cuda.synchronize()
-                check(orc, Xw, mean.cpu().numpy(), {d: K[d].cpu().numpy() for d in K}, d_max, b, TOL[prec], shift)
+                check(orc, Xw, mean.cpu().numpy(), {d: K[d].cpu().numpy() for d in K}, d_max, b, TOL[prec], prec, shift)
     finally:
         st.close()

@@ -5,14 +5,16 @@ configuration before it runs.
 
 The error of order d is e_d, relative to the largest oracle entry of that
 order (with t = 2 the odd cumulants vanish in exact arithmetic and are
-scaled by the moments instead: tests/errmeasure.py)."""
+scaled by the moments instead), held to the path's target; the FP32-staged
+paths on fewer than 500 samples are held to the target times the
+cancellation max|M_d| / max|kappa_d| (tests/errmeasure.py)."""
 import sys
 
 import numpy as np
 import pytest
 
 import workloads
-from errmeasure import e_d
+from errmeasure import bound, e_d
 
 pytestmark = pytest.mark.gpu
 
@@ -70,5 +72,6 @@ def test_random_configuration(dev, orc, n, b, d_max, t, prec, inner, shape, targ
             assert not np.any(got), d
             continue
         e = e_d(got, want, d, X - om)
-        print(f"  e_{d} = {e:.3e}", file=sys.stderr, flush=True)
-        assert e <= TOL[prec], (d, e)
+        tol = bound(TOL[prec], prec, t, orc, X - om, OK[d], d)
+        print(f"  e_{d} = {e:.3e} (tolerance {tol:.3e})", file=sys.stderr, flush=True)
+        assert e <= tol, (d, e, tol)

@@ -166,12 +166,12 @@ def test_tune_file_is_read_and_bad_lines_skipped(tmp_path):
     f.write_text("12 3 2 4 1 1000 2 4096 2\n"     # valid
                  "12 3 2 5 1 1000 2 4096\n"       # too few fields
                  "12 3 2 6 1 1000 2 4096 7\n"     # inner_b > b
-                 "12 3 2 7 1 1000 5 4096 1\n")    # unknown shape
+                 "12 3 2 3 1 1000 5 4096 1\n")    # unknown shape
     code = ("import paper_1701_05420_amd as pc\n"
             "print(pc.get_tuning(1000, 12, 4, 3, 'f32'))\n"
             "print(pc.get_tuning(1000, 12, 5, 3, 'f32'))\n"
             "print(pc.get_tuning(1000, 12, 6, 3, 'f32'))\n"
-            "print(pc.get_tuning(1000, 12, 7, 3, 'f32'))\n")
+            "print(pc.get_tuning(1000, 12, 3, 3, 'f32'))\n")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     env = dict(os.environ, CUM_TUNE_FILE=str(f), PYTHONPATH=root)
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True,
@@ -207,7 +207,8 @@ def test_missing_library_fails_loudly(tmp_path):
     pkg.mkdir()
     shutil.copy(os.path.join(ROOT, "paper_1701_05420_amd", "__init__.py"), pkg / "__init__.py")
     out = subprocess.run([sys.executable, "-c", "import paper_1701_05420_amd"], cwd=tmp_path,
-                         env=dict(os.environ, PYTHONPATH=str(tmp_path)), capture_output=True, text=True, timeout=120)
+                         env=dict({k: v for k, v in os.environ.items() if k != "CUM_LIBRARY"},
+                                  PYTHONPATH=str(tmp_path)), capture_output=True, text=True, timeout=120)
     assert out.returncode != 0
     assert "ImportError" in out.stderr and "no fallback" in out.stderr
 
@@ -246,3 +247,15 @@ def test_blocks_beyond_32_bit_entries_are_refused(pc):
         assert _raw(pc, "cum_batch_create", 2, ts, n, 10, b, 1, ctypes.byref(h)) == -4
     # within 32 bits the layout is reported exactly
     assert pc.layout(100, 4, 97)["block_elems"] == 97 ** 4
+
+
+def test_orders_7_and_above_stage_in_fp64(pc):
+    """A call that centres its own data with d_max >= 7 stages and contracts
+    in FP64 in every precision: its workspace and its plan are those of the
+    FP64 call, while d_max = 6 keeps the precision asked for."""
+    t, n, b = 20_000, 8, 2
+    for prec in ("f32", "bf16x2", "bf16x3"):
+        for dmax in (7, 10):
+            assert pc.workspace_size(t, n, dmax, b, prec) == pc.workspace_size(t, n, dmax, b, "f64")
+            assert pc.plan_info(t, n, dmax, b, prec) == pc.plan_info(t, n, dmax, b, "f64")
+        assert pc.workspace_size(t, n, 6, b, prec) < pc.workspace_size(t, n, 6, b, "f64")
