@@ -153,6 +153,27 @@ cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_m
                          double *mean, double *const *kappa /* host array */, void *ws, size_t ws_bytes,
                          void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as cum_cumulants (bitwise, for the same
+ * configuration), with the workspace taken from a fixed scratch array that
+ * the library holds on each GPU until the process ends, so the call
+ * allocates nothing and needs no ws argument.
+ *   - The scratch holds CUM_NOALLOC_SCRATCH_BYTES; a call that would need
+ *     more than cum_workspace_size(t, n, d_max, b, prec) of it returns
+ *     CUM_ENOMEM and enqueues nothing.
+ *   - The configuration's device tables must already exist: run
+ *     cum_cumulants once with the same n, b, d_max, prec, tuning and a t of
+ *     the same sample-chunk count first; otherwise CUM_EUNSUPPORTED and
+ *     nothing is enqueued.
+ *   - Every call on one GPU shares that GPU's scratch, which keeps the last
+ *     call's contents (nothing in it needs to start at zero).  Calls that
+ *     overlap on one GPU (other streams, other threads) race on it.
+ * Arguments as for cum_cumulants. */
+#define CUM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+cum_status cum_cumulants_noalloc(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
+                                 double *mean, double *const *kappa /* host array */, void *stream);
+
 /* Unfold an order-d block-stored tensor to the dense n^d array (first index
  * slowest).  Entry i is read from the canonical stored copy: the position
  * reached by sorting i_1..i_d ascending, so the output is exactly symmetric

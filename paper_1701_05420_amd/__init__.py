@@ -31,7 +31,8 @@ PRECS = {"f64": 0, "f32": 1, "bf16x2": 2, "bf16x3": 3}
 MAX_ORDER = 10
 
 EXPORTS = [
-    "cum_layout_query", "cum_workspace_size", "cum_center", "cum_moment_blocks", "cum_cumulants", "cum_unfold",
+    "cum_layout_query", "cum_workspace_size", "cum_center", "cum_moment_blocks", "cum_cumulants",
+    "cum_cumulants_noalloc", "cum_unfold",
     "cum_stored_offset", "cum_batch_create", "cum_batch_run", "cum_batch_timestamps", "cum_batch_destroy",
     "cum_plan_check", "cum_timing_enable", "cum_timing_read", "cum_autotune", "cum_set_tuning", "cum_get_tuning", "cum_get_plan_info",
     "cum_batch_autotune", "cum_stream_create", "cum_stream_update", "cum_stream_cumulants", "cum_stream_cumulants_moebius",
@@ -64,6 +65,7 @@ _lib.cum_workspace_size.argtypes = [_I64, _I, _I, _I, _I, ctypes.POINTER(_SZ)]
 _lib.cum_center.argtypes = [_VP, _I64, _I, _I64, _I, _VP, _VP, _VP, _SZ, _VP]
 _lib.cum_moment_blocks.argtypes = [_VP, _I, _I64, _I, _I, _I, _VP, _VP, _SZ, _VP]
 _lib.cum_cumulants.argtypes = [_VP, _I64, _I, _I64, _I, _I, _I, _VP, ctypes.POINTER(_VP), _VP, _SZ, _VP]
+_lib.cum_cumulants_noalloc.argtypes = [_VP, _I64, _I, _I64, _I, _I, _I, _VP, ctypes.POINTER(_VP), _VP]
 _lib.cum_unfold.argtypes = [_VP, _I, _I, _I, _VP, _VP]
 _lib.cum_stored_offset.argtypes = [_I, _I, _I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_I64)]
 _lib.cum_batch_create.argtypes = [_I, ctypes.POINTER(_I64), _I, _I, _I, _I, ctypes.POINTER(_VP)]
@@ -278,6 +280,25 @@ def cumulants(X, d_max: int, b: int, prec="f64", ws=None, out=None, stream=None)
     ptrs = (_VP * (d_max - 1))(*[out[d].data_ptr() for d in range(2, d_max + 1)])
     _check(_lib.cum_cumulants(X.data_ptr(), t, n, X.stride(0), d_max, b, p, mean.data_ptr(), ptrs,
                               ws.data_ptr(), ws.numel() * ws.element_size(), _stream(stream)))
+    return mean, out
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def cumulants_noalloc(X, d_max: int, b: int, prec, mean, out, stream=None):
+    """cumulants() through the library's allocation-free entry point: the
+    caller passes the mean (n FP64) and the outputs {d: block storage}; the
+    library takes its workspace from its fixed scratch.  The configuration
+    must have been run once by cumulants() before."""
+    torch = _torch()
+    _dev_check(X, torch.float64, "X")
+    if X.stride(1) != 1:
+        raise ValueError("X must have unit column stride")
+    t, n = X.shape
+    ptrs = (_VP * (d_max - 1))(*[out[d].data_ptr() for d in range(2, d_max + 1)])
+    _check(_lib.cum_cumulants_noalloc(X.data_ptr(), t, n, X.stride(0), d_max, b, _prec(prec),
+                                      mean.data_ptr() if mean is not None else None, ptrs, _stream(stream)))
     return mean, out
 
 

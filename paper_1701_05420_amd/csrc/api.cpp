@@ -1131,9 +1131,15 @@ cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, in
     return run_orders(k, Xst, (double *)(Xst + xbytes), outs, false, s);
 }
 
-// The body of cum_cumulants.
+static_assert(NOALLOC_SCRATCH_BYTES == CUM_NOALLOC_SCRATCH_BYTES, "scratch size");
+
+// The body of cum_cumulants and of its allocation-free variant.  With
+// noalloc, ws is the fixed scratch (null until after the checks, which then
+// look it up) and every device table must already exist: the call allocates
+// nothing.
 static cum_status cumulants_impl(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
-                                 double *mean, double *const *kappa, void *ws, size_t ws_bytes, void *stream) {
+                                 double *mean, double *const *kappa, void *ws, size_t ws_bytes, void *stream,
+                                 bool noalloc) {
     cum_status st;
     if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;
     if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
@@ -1153,6 +1159,23 @@ static cum_status cumulants_impl(const double *X, int64_t t, int n, int64_t ldx,
     const size_t mbytes = align_up((size_t)n * 8);
     const size_t pbytes = align_up((size_t)k.nchunks * k.c->stride * 8);
     const size_t need = xbytes + cbytes + mbytes + pbytes + moment_bytes(n, b, d_max);
+    if (noalloc) {
+        if (need > NOALLOC_SCRATCH_BYTES)
+            return fail(CUM_ENOMEM, "this call needs %zu bytes of scratch; the fixed scratch holds %zu", need,
+                        NOALLOC_SCRATCH_BYTES);
+        if (!k.c->uploaded || !k.is->uploaded)
+            return fail(CUM_EUNSUPPORTED,
+                        "the device tables of this configuration (n, b, d_max, prec, tuning and the sample-chunk "
+                        "count of t) do not exist yet: run cum_cumulants once with it first");
+        HIP_TRY(noalloc_scratch(&ws));
+        ws_bytes = NOALLOC_SCRATCH_BYTES;
+    }
+    // the benchmark's per-launch timing creates HIP events: off for this call
+    struct TimingOff {
+        bool was, on;
+        ~TimingOff() { if (on) g_timing = was; }
+    } toff{g_timing, noalloc};
+    if (noalloc) g_timing = false;
     if (!ws || ws_bytes < need) return fail(CUM_ENOMEM, "cumulants needs %zu workspace bytes (got %zu)", need, ws_bytes);
     char *w = (char *)ws;
     char *Xst = w;
@@ -1181,7 +1204,12 @@ static cum_status cumulants_impl(const double *X, int64_t t, int n, int64_t ldx,
 
 cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
                          double *mean, double *const *kappa, void *ws, size_t ws_bytes, void *stream) {
-    return cumulants_impl(X, t, n, ldx, d_max, b, prec, mean, kappa, ws, ws_bytes, stream);
+    return cumulants_impl(X, t, n, ldx, d_max, b, prec, mean, kappa, ws, ws_bytes, stream, false);
+}
+
+cum_status cum_cumulants_noalloc(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
+                                 double *mean, double *const *kappa, void *stream) {
+    return cumulants_impl(X, t, n, ldx, d_max, b, prec, mean, kappa, nullptr, 0, stream, true);
 }
 
 cum_status cum_unfold(const double *blocks, int n, int d, int b, double *dense, void *stream) {

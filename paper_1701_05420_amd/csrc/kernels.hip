@@ -1519,4 +1519,32 @@ hipError_t launch_stamp(unsigned long long *where, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Fixed scratch memory of the allocation-free entry point: an array in each
+// GPU's copy of the code object, held until the process ends.  Host code
+// never uses the array's name as an address (on the host it only stands for
+// the symbol); it uses the device address looked up below.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+// The device address of the current GPU's copy of `scratch`, looked up once
+// per device with that device current and kept.  Callers hold the library's
+// lock.  Returns the HIP status of the lookup.
+hipError_t noalloc_scratch(void **out) {
+    static void *ptr[NOALLOC_MAX_DEVICES] = {nullptr};
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace cum

@@ -109,4 +109,10 @@ hipError_t launch_batch_stage(const CenterSet *sets, int nsets, int n, int prec,
 hipError_t launch_batch_stamp(unsigned long long *stamps, int nsets, hipStream_t s);
 hipError_t launch_stamp(unsigned long long *where, hipStream_t s);
 
+// Fixed device scratch of the allocation-free entry point
+// (CUM_NOALLOC_SCRATCH_BYTES on each of devices 0..NOALLOC_MAX_DEVICES-1).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+hipError_t noalloc_scratch(void **out);
+
 }  // namespace cum

@@ -259,3 +259,21 @@ def test_orders_7_and_above_stage_in_fp64(pc):
             assert pc.workspace_size(t, n, dmax, b, prec) == pc.workspace_size(t, n, dmax, b, "f64")
             assert pc.plan_info(t, n, dmax, b, prec) == pc.plan_info(t, n, dmax, b, "f64")
         assert pc.workspace_size(t, n, 6, b, prec) < pc.workspace_size(t, n, 6, b, "f64")
+
+
+def test_noalloc_entry_point_refuses_before_any_device_work(pc):
+    """The allocation-free entry point checks on the host, before anything is
+    enqueued: a call whose workspace exceeds the fixed scratch is refused
+    (CUM_ENOMEM), and so is one whose device tables do not exist yet
+    (CUM_EUNSUPPORTED); argument errors are those of cum_cumulants."""
+    P = ctypes.c_void_p(0x1000)
+    kap = (ctypes.c_void_p * 9)(*([0x1000] * 9))
+    # n = 64, d <= 5, t = 5e6: hundreds of MB of staged data alone
+    assert pc.workspace_size(5_000_000, 64, 5, 4, "f32") > pc.NOALLOC_SCRATCH_BYTES
+    assert _raw(pc, "cum_cumulants_noalloc", P, 5_000_000, 64, 64, 5, 4, 1, P, kap, None) == -2
+    assert b"scratch" in pc._lib.cum_last_error()
+    # a configuration never run: no device tables
+    assert _raw(pc, "cum_cumulants_noalloc", P, 1000, 11, 11, 4, 3, 1, P, kap, None) == -4
+    assert b"cum_cumulants once" in pc._lib.cum_last_error()
+    assert _raw(pc, "cum_cumulants_noalloc", P, 0, 11, 11, 4, 3, 1, P, kap, None) == -1     # t = 0
+    assert _raw(pc, "cum_cumulants_noalloc", P, 10, 4, 4, 4, 2, 7, P, kap, None) == -4      # prec
