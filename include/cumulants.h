@@ -245,12 +245,19 @@ cum_status cum_get_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, cum
 
 /* ------------------------------------------------------------------------
  * Batched cumulants: many datasets of the same width n and uneven sample
- * counts, computed by one persistent launch of the moment contraction over
- * all (dataset, tile, sample-chunk) work items, between one batched centring
- * launch and one batched reduction/recursion launch per pair of orders, all
- * captured once in a HIP graph and replayed.  Results are deterministic
- * (the same plan gives bitwise the same output on every run) and carry the
- * accuracy of cum_cumulants() for the same prec.
+ * counts, captured once in a HIP graph and replayed: one batched centring
+ * launch, then the datasets in groups of about equal work (up to 8; large
+ * batches only).  Each group is one launch of the moment contraction over
+ * its (dataset, tile, sample-chunk) work items, in group order; a group's
+ * chunk sums and finalisation (reduction and recursion, one launch per pair
+ * of orders; orders 7 and above by the first-position formula over each
+ * dataset's lower central moments) run on a second stream as soon as its
+ * contraction is done, beside the next group's contraction, so the first
+ * groups' results are ready before the whole batch is.  The environment
+ * variable CUM_BATCH_GROUPS, read when a plan is laid out, fixes the group
+ * count.  Results are deterministic (the same plan gives bitwise the same
+ * output on every run, and the group count does not change the bits) and
+ * carry the accuracy of cum_cumulants() for the same prec.
  * ------------------------------------------------------------------------ */
 typedef struct cum_batch cum_batch;
 

@@ -8,20 +8,15 @@ noise.  There, and only there, the scale is s_d = max_i mean_l |x~_li|^d,
 which bounds every entry of M_d (Hoelder's inequality).
 
 The tolerance e_d is held to (``bound``) is the path's target (1e-10 FP64,
-1e-6 FP32 and the three-term BF16 split, 5e-5 the two-term split) with one
-exception, for the FP32-staged paths on fewer than FEW_SAMPLES samples.  They
-sum each stage of 64 samples in FP32 before carrying the sum into FP64, so a
-moment carries up to about 16 roundings of 2^-24 relative to itself.  With
-many stages those average out; with one or a few stages they do not, and the
-cumulant inherits them amplified by the cancellation of its recursion,
-rho_d = max|M_d| / max|kappa_d|.  There the tolerance is tol * max(1, rho_d):
-measured on a 63-sample case, e_4 = 1.65e-6 at rho_4 = 2.47, and a CPU
-emulation of the same FP32 sums gives 1.3e-6, against 1.2e-7 from rounding
-the data to FP32 alone."""
+1e-6 FP32 and the three-term BF16 split, 5e-5 the two-term split), times
+max(1, rho_d) for the FP32-staged paths, rho_d = max|M_d| / max|kappa_d|.
+Those paths sum each stage of 64 samples in FP32 before carrying the sum into
+FP64, so a moment carries FP32 roundings relative to the moment itself; the
+cumulant inherits them amplified by the cancellation of its recursion, rho_d.
+Measured: e_4 = 1.65e-6 at rho_4 = 2.47 on 63 samples (a CPU emulation of the
+same FP32 sums gives 1.3e-6; rounding the data to FP32 alone 1.2e-7), and
+e_5 = 1.14e-6 at rho_5 = 2.63 on 1434 samples."""
 import numpy as np
-
-FEW_SAMPLES = 500
-
 
 def e_d(got, want, d, Xc=None):
     """Relative error of order d.  Xc: the centred samples the cumulants are
@@ -46,8 +41,8 @@ def rho(orc, Xc, kappa_dense, d):
 
 def bound(tol, prec, t, orc=None, Xc=None, kappa_dense=None, d=None):
     """The tolerance of e_d for a path of precision prec on t samples (see
-    the module text): tol, times max(1, rho_d) for the FP32-staged paths on
-    fewer than FEW_SAMPLES samples."""
-    if prec == "f64" or t >= FEW_SAMPLES or orc is None:
+    the module text): tol, times max(1, rho_d) for the FP32-staged paths."""
+    if prec == "f64" or orc is None or t <= 2:
+        # (with two samples the odd orders are scaled by s_d in e_d already)
         return tol
     return tol * max(1.0, rho(orc, Xc, kappa_dense, d))

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import workloads
+from errmeasure import bound, e_d
 
 pytestmark = pytest.mark.gpu
 
@@ -121,8 +122,9 @@ def test_batch_workload_sampled(dev, orc):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_batch_high_order_integer_exact(dev, orc, prec):
-    """Batches keep the partition recursion at every order: orders to 9, with
-    its 3425-partition table, bit-exact on small-integer data."""
+    """Orders to 9 in a batch (orders 7 and above by the first-position
+    formula over each dataset's lower central moments), bit-exact on
+    small-integer data."""
     torch, pc = dev
     n, b, dmax = 3, 2, 9
     ts = [64, 32, 128, 16]
@@ -159,3 +161,40 @@ def test_batch_high_order_float(dev, orc):
             e = rel(K[s][d].cpu().numpy(), orc.fold(OK[d], b))
             assert e <= 1e-10, (s, d, e)
     batch.close()
+
+
+@pytest.mark.parametrize("groups", [3, 8])
+def test_batch_groups_bitwise_and_oracle(dev, orc, groups, monkeypatch):
+    """Datasets finalised in groups (each group's chunk sum and finalisation
+    on a side stream beside the next group's contraction) give bitwise the
+    results of one group, which match the oracle; replays keep the bits and
+    every dataset gets its finalisation stamp."""
+    torch, pc = dev
+    n, b, dmax = 7, 3, 5
+    rng = np.random.default_rng(groups)
+    ts = [int(x) for x in rng.integers(1, 2500, size=19)] + [1, 64]
+    say(f"batch groups={groups} sets={len(ts)} n={n} b={b} d_max={dmax}")
+    Xs = [workloads.t_gamma_mix(t=t, n=n, seed=700 + i) for i, t in enumerate(ts)]
+    Xd = [torch.from_numpy(X).cuda() for X in Xs]
+    monkeypatch.setenv("CUM_BATCH_GROUPS", "1")
+    one = pc.Batch(ts, n, dmax, b, "f32")
+    _, K1 = one.run(Xd)
+    monkeypatch.setenv("CUM_BATCH_GROUPS", str(groups))
+    grp = pc.Batch(ts, n, dmax, b, "f32")
+    for rep in range(2):
+        _, K = grp.run(Xd)
+        torch.cuda.synchronize()
+        for s in range(len(ts)):
+            for d in range(2, dmax + 1):
+                assert torch.equal(K[s][d], K1[s][d]), (rep, s, d)
+    start, ticks, hz = grp.timestamps()
+    assert hz > 0 and all(tk > start for tk in ticks)
+    for s, X in enumerate(Xs):
+        if ts[s] < 2:
+            continue
+        om, OK = orc.cumulants_dense(X, dmax)
+        for d in range(2, dmax + 1):
+            e = e_d(K[s][d].cpu().numpy(), orc.fold(OK[d], b), d, X - om)
+            assert e <= bound(1e-6, "f32", ts[s], orc, X - om, OK[d], d), (s, ts[s], d, e)
+    one.close()
+    grp.close()

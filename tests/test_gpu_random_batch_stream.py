@@ -5,9 +5,9 @@ Each case prints its configuration before it runs.
 
 Errors are e_d, relative to the largest oracle entry of each order (with two
 samples the odd cumulants vanish in exact arithmetic and are scaled by the
-moments instead), held to the path's target; the FP32-staged paths on fewer
-than 500 samples are held to the target times the cancellation
-max|M_d| / max|kappa_d| (tests/errmeasure.py)."""
+moments instead), held to the path's target; the FP32-staged paths are held to
+the target times the cancellation max|M_d| / max|kappa_d|
+(tests/errmeasure.py)."""
 import sys
 
 import numpy as np

@@ -6,8 +6,8 @@ configuration before it runs.
 The error of order d is e_d, relative to the largest oracle entry of that
 order (with t = 2 the odd cumulants vanish in exact arithmetic and are
 scaled by the moments instead), held to the path's target; the FP32-staged
-paths on fewer than 500 samples are held to the target times the
-cancellation max|M_d| / max|kappa_d| (tests/errmeasure.py)."""
+paths are held to the target times the cancellation max|M_d| / max|kappa_d|
+(tests/errmeasure.py)."""
 import sys
 
 import numpy as np
