@@ -225,13 +225,14 @@ struct OrderPlan {
     std::vector<int32_t> parts;   // npart x (d/2), packed mask | where << 10
     int npart = 0;
     std::vector<int32_t> terms;   // orders >= 7: nterm x 2 (set A with position 0, its complement)
+    std::vector<int32_t> tpw;     // their multipliers b^|high positions| (see RedOrder::tpw)
     int nterm = 0;
     std::vector<uint16_t> smask;  // position sets of 2..d-2 positions, by size then value
     std::vector<int32_t> gmap;    // staged slot -> s | flat << 10
     int32_t mstart[MAXD] = {0};   // first staged slot of each set size m (index m - 2)
     int lds_elems = 0;            // 0: the recursion reads lower orders from memory
     bool uploaded = false;
-    DevBuf rows_d, cols_d, H_d, prank_d, tuples_d, parts_d, smask_d, gmap_d, terms_d;
+    DevBuf rows_d, cols_d, H_d, prank_d, tuples_d, parts_d, smask_d, gmap_d, terms_d, tpw_d;
 };
 
 // Cut points of the sorted rows (or columns) into 16-blocks.  A 16 x 16
@@ -473,6 +474,7 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
             for (int f : {mask, comp}) {
                 const int where = o.lds_elems ? (int)soff[(size_t)sidx[f]] : sidx[f];
                 o.terms.push_back((int32_t)f | (int32_t)(where << 10));
+                o.tpw.push_back((int32_t)ipow64(b, __builtin_popcount((unsigned)f >> ((d + 1) / 2))));
             }
         }
         o.nterm = (int)o.terms.size() / 2;
@@ -487,7 +489,7 @@ static cum_status upload_order(OrderPlan &o) {
     if ((st = upload(o.rows_d, o.rows)) || (st = upload(o.cols_d, o.cols)) || (st = upload(o.H_d, o.H)) || (st = upload(o.prank_d, o.prank)) ||
         (st = upload(o.tuples_d, o.tuples)) ||
         (st = upload(o.parts_d, o.parts)) || (st = upload(o.smask_d, o.smask)) ||
-        (st = upload(o.gmap_d, o.gmap)) || (st = upload(o.terms_d, o.terms)))
+        (st = upload(o.gmap_d, o.gmap)) || (st = upload(o.terms_d, o.terms)) || (st = upload(o.tpw_d, o.tpw)))
         return st;
     o.uploaded = true;
     return CUM_OK;
@@ -587,6 +589,7 @@ static RedOrder red_order(const OrderPlan &o, const OrderPlan &po, int64_t poff)
     ro.smask = (const uint16_t *)o.smask_d.p;
     ro.gmap = (const int32_t *)o.gmap_d.p;
     ro.terms = (const int32_t *)o.terms_d.p;
+    ro.tpw = (const int32_t *)o.tpw_d.p;
     ro.nterm = o.nterm;
     ro.prank = (const int64_t *)po.prank_d.p;
     ro.ns = (int32_t)o.smask.size();
@@ -1333,6 +1336,12 @@ cum_status cum_plan_check(int n, int d, int b) {
                     return fail(CUM_EINVAL, "d=%d: set index of factor %d of term %d", d, k, z);
                 }
                 masks2[k] = (int)mask;
+                // the multiplier of the set's index: b^(positions from ceil(d/2) on)
+                int64_t pw = 1;
+                for (int k2 = (d + 1) / 2; k2 < d; ++k2)
+                    if (mask >> k2 & 1u) pw *= b;
+                if ((int)o.tpw.size() != 2 * o.nterm || o.tpw[(size_t)z * 2 + k] != pw)
+                    return fail(CUM_EINVAL, "d=%d: multiplier of factor %d of term %d", d, k, z);
             }
             if (!(masks2[0] & 1) || (masks2[0] ^ masks2[1]) != (1 << d) - 1 || (masks2[0] & masks2[1]))
                 return fail(CUM_EINVAL, "d=%d: term %d is not a set with position 0 and its complement", d, z);

@@ -870,6 +870,7 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
     __syncthreads();  // the previous block's readers are done with the LDS tables
     if (tid < D) tup[tid] = gmem(ro.tuples)[B * D + tid];
     const CUM_CONST int32_t *terms_g = cmem(ro.terms);
+    const CUM_CONST int32_t *tpw_g = cmem(ro.tpw);
     if (parts_in_lds) {
         if (first_pos)
             for (int i = tid; i < ro.nterm * 2; i += NT) parts_l[i] = terms_g[i];
@@ -986,17 +987,58 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
             }
             M[q] = S / tt;
         }
+        // One entry per thread: the in-block index of the entry's digits at
+        // the positions of any set, from two tables built once per entry.
+        // Positions 0..HL-1 index tlo, positions HL..D-1 index thi (by the set
+        // mask shifted down by HL); each table entry follows from the one
+        // without its last position by one step of Horner's rule, and a set's
+        // index is tlo[low part] * b^|high part| + thi[high part].
+        constexpr int HL = (D + 1) / 2, HH = D - HL;
+        unsigned tlo[1 << HL], thi[1 << HH];
+        const unsigned b2 = b * b, b4 = b2 * b2;  // b^|high part| = b^(c&1) b2^(c>>1&1) b4^(c>>2), c <= 5
+        if constexpr (EPT == 1) {
+            tlo[0] = 0;
+#pragma unroll
+            for (int m = 1; m < (1 << HL); ++m) {
+                const int k = 31 - __builtin_clz((unsigned)m);
+                tlo[m] = __umul24(tlo[m & ~(1 << k)], b) + (unsigned)r[0][k];
+            }
+            thi[0] = 0;
+#pragma unroll
+            for (int m = 1; m < (1 << HH); ++m) {
+                const int k = 31 - __builtin_clz((unsigned)m);
+                thi[m] = __umul24(thi[m & ~(1 << k)], b) + (unsigned)r[0][HL + k];
+            }
+        }
         // One factor of a term for every entry of the thread: the lower-order
         // sub-block of part pk (position mask | where << 10), read in LDS
         // (staged) or in memory, where first-position formula factors without
         // position 0 are central moments.  The part is the same for every lane:
         // readfirstlane makes that explicit, so that the position tests are
         // scalar.
-        auto factor = [&](auto staged_t, int pk0, double (&v)[EPT]) {
+        // pw0: the set's multiplier b^|high part| when the table gives it (the
+        // first-position terms), else negative
+        auto factor = [&](auto staged_t, int pk0, double (&v)[EPT], int pw0 = -1) {
             constexpr bool ST = decltype(staged_t)::value;
             const int pk = __builtin_amdgcn_readfirstlane(pk0);
             const unsigned mask = (unsigned)pk & 1023u;
             const int where = pk >> 10;
+            if constexpr (EPT == 1) {
+                const unsigned lo = mask & ((1u << HL) - 1u), hi = mask >> HL;
+                unsigned pw;
+                if (pw0 >= 0) {
+                    pw = (unsigned)__builtin_amdgcn_readfirstlane(pw0);
+                } else {
+                    const unsigned c = __builtin_popcount(hi);
+                    pw = ((c & 1u) ? b : 1u) * ((c & 2u) ? b2 : 1u) * ((c & 4u) ? b4 : 1u);
+                }
+                const unsigned flat = __umul24(tlo[lo], pw) + thi[hi];
+                if constexpr (ST)
+                    v[0] = sub[where + flat];
+                else
+                    v[0] = gmem(base[where])[flat];
+                return;
+            }
             // In-block index of the sub-block entry, by Horner's rule over the
             // digits of the set's positions.  A set has at most D - 2
             // positions, so every product below is of a value under b^(D-3)
@@ -1029,12 +1071,14 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
                 // one entry per thread: eight terms' parts in one scalar read,
                 // then their sixteen loads in flight at once
                 for (; z + 8 <= ro.nterm; z += 8) {
-                    int pk[16];
+                    int pk[16], pw[16];
 #pragma unroll
                     for (int i = 0; i < 16; ++i) pk[i] = terms_g[z * 2 + i];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) pw[i] = tpw_g[z * 2 + i];
                     double v[16][EPT];
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) factor(staged_t, pk[i], v[i]);
+                    for (int i = 0; i < 16; ++i) factor(staged_t, pk[i], v[i], pw[i]);
 #pragma unroll
                     for (int u = 0; u < 8; ++u) sum[0] += v[2 * u][0] * v[2 * u + 1][0];
                 }

@@ -114,6 +114,8 @@ struct RedOrder {
                              // the index of the part's position set in smask (others)
     const uint16_t *smask;   // ns position sets S of 2..d-2 positions, by size then value
     const int32_t *gmap;     // lds_elems staged slots: s | flat << 10, grouped by |S|
+    const int32_t *tpw;      // orders >= 7: nterm x 2 multipliers b^|S & ~(2^h - 1)|, h = ceil(d/2), of the
+                             // factors' sets (the in-block index of a set is tlo * that + thi)
     const int32_t *terms;    // orders >= 7: nterm x 2 factors (a set A holding the first position
                              // and its complement C), packed mask | where << 10 like parts
     const int64_t *prank;    // d x (pnbar + 1) rank terms of the partial-sum layout:
