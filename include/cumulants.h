@@ -246,8 +246,8 @@ cum_status cum_get_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, cum
 /* ------------------------------------------------------------------------
  * Batched cumulants: many datasets of the same width n and uneven sample
  * counts, captured once in a HIP graph and replayed: one batched centring
- * launch, then the datasets in groups of about equal work (up to 8; large
- * batches only).  Each group is one launch of the moment contraction over
+ * launch, then the datasets in groups of about equal work (one group per 128
+ * datasets, at most 4).  Each group is one launch of the moment contraction over
  * its (dataset, tile, sample-chunk) work items, in group order; a group's
  * chunk sums and finalisation (reduction and recursion, one launch per pair
  * of orders; orders 7 and above by the first-position formula over each
@@ -255,7 +255,7 @@ cum_status cum_get_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, cum
  * contraction is done, beside the next group's contraction, so the first
  * groups' results are ready before the whole batch is.  The environment
  * variable CUM_BATCH_GROUPS, read when a plan is laid out, fixes the group
- * count.  Results are deterministic (the same plan gives bitwise the same
+ * count (at most 8).  Results are deterministic (the same plan gives bitwise the same
  * output on every run, and the group count does not change the bits) and
  * carry the accuracy of cum_cumulants() for the same prec.
  * ------------------------------------------------------------------------ */

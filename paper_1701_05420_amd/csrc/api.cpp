@@ -1605,14 +1605,15 @@ cum_status cum_timing_read(double *ms, int64_t *launches) {
 // ---------------------------------------------------------------------------
 // Batched cumulants.
 // ---------------------------------------------------------------------------
-// Largest number of dataset groups of a batch, and the contraction items a
-// group should hold at least (four rounds of the 1024 work-group slots).
-// On the 512-dataset workload (n = 32, d <= 4), 4 groups left the batch time
-// unchanged (5.37 against 5.33 ms) and took the median dataset's latency
-// from 4.82 to 4.30 ms; 8 groups gave 3.89 ms but a 10 % longer batch (each
-// group's contraction ends in a tail).
+// Dataset groups of a batch: one per BATCH_SETS_PER_GROUP datasets, at most
+// BATCH_GROUPS (and up to BATCH_MAX_GROUPS when fixed by CUM_BATCH_GROUPS).
+// On the 512-dataset workload (n = 32, d <= 4, 16384 target items), 4 groups
+// left the batch time unchanged (5.37 against 5.33 ms) and took the median
+// dataset's latency from 4.82 to 4.30 ms; 8 groups gave 3.89 ms but a 10 %
+// longer batch (each group's contraction ends in a tail).
 constexpr int BATCH_MAX_GROUPS = 8;
-constexpr int64_t BATCH_GROUP_ITEMS = 4096;
+constexpr int BATCH_GROUPS = 4;
+constexpr int BATCH_SETS_PER_GROUP = 128;
 
 struct cum_batch {
     int nsets = 0, n = 0, d_max = 0, b = 0, bi = 0, prec = 0, shape = 0;
@@ -1757,18 +1758,15 @@ static cum_status batch_layout(cum_batch &p, int bi, int shape, int target) {
         sd.partial = reinterpret_cast<double *>(poff);  // offset; rebased after allocation
         poff += sd.nchunks * p.stride;
     }
-    // groups of consecutive datasets of about equal contraction work, each
-    // with enough items to fill the GPU several times over
+    // groups of consecutive datasets of about equal contraction work
     int64_t tile_cost = 0, work = 0;
     for (auto &h : p.tiles) tile_cost += h.cost;
     std::vector<int64_t> cum_work(p.nsets + 1, 0);
-    int64_t all_items = 0;
     for (int s = 0; s < p.nsets; ++s) {
         work += p.sets[s].nstages * tile_cost;
         cum_work[s + 1] = work;
-        all_items += p.sets[s].nchunks * ntiles;
     }
-    int64_t want_groups = all_items / BATCH_GROUP_ITEMS;
+    int64_t want_groups = std::min<int64_t>(BATCH_GROUPS, p.nsets / BATCH_SETS_PER_GROUP);
     if (const char *e = getenv("CUM_BATCH_GROUPS")) {  // a fixed group count (tests, experiments)
         const long v = strtol(e, nullptr, 10);
         if (v >= 1) want_groups = v;
