@@ -1640,14 +1640,18 @@ struct cum_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool pending_copy = false;
-    // Datasets are finalised in groups: group g's datasets are group_first[g]
-    // .. group_first[g+1]-1, and its contraction items are items
+    // Datasets are finalised in groups: group g's datasets are seq[group_first[g]]
+    // .. seq[group_first[g+1]-1], and its contraction items are items
     // group_item[g] .. group_item[g+1]-1.  The contraction of the groups runs
     // in group order on the plan's stream; each group's chunk sum and
     // finalisation run on the side stream as soon as its contraction is done,
     // beside the next group's contraction.
     int ngroups = 1;
     std::vector<int> group_first;
+    // The datasets in group order: by sample count, smallest first (shortest
+    // work first gives the least mean completion time), then by index.  The
+    // device array of finalisation records (setred_d) is in this order.
+    std::vector<int> seq;
     std::vector<int64_t> group_item;
     hipStream_t side = nullptr;
     std::vector<hipEvent_t> group_done;  // capture-time fork events, one per group
@@ -1684,9 +1688,9 @@ static std::vector<Item> batch_items(const cum_batch &p, int s0, int s1) {
     int64_t tile_cost = 0;
     for (auto &h : p.tiles) tile_cost += h.cost;
     std::vector<int> order;
-    for (int s = s0; s < s1; ++s) order.push_back(s);
+    for (int i = s0; i < s1; ++i) order.push_back(p.seq[i]);
     std::vector<int64_t> nst(p.nsets);
-    for (int s = s0; s < s1; ++s) nst[s] = p.sets[s].nstages;
+    for (int s : order) nst[s] = p.sets[s].nstages;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nst[x] > nst[y]; });
     int64_t load[8] = {0};
     std::vector<std::vector<std::pair<int64_t, Item>>> per_xcd(8);
@@ -1758,13 +1762,18 @@ static cum_status batch_layout(cum_batch &p, int bi, int shape, int target) {
         sd.partial = reinterpret_cast<double *>(poff);  // offset; rebased after allocation
         poff += sd.nchunks * p.stride;
     }
-    // groups of consecutive datasets of about equal contraction work
+    // groups of about equal contraction work, consecutive in the order of
+    // increasing sample count
+    p.seq.resize(p.nsets);
+    for (int s = 0; s < p.nsets; ++s) p.seq[s] = s;
+    std::stable_sort(p.seq.begin(), p.seq.end(),
+                     [&](int x, int y) { return p.sets[x].nstages < p.sets[y].nstages; });
     int64_t tile_cost = 0, work = 0;
     for (auto &h : p.tiles) tile_cost += h.cost;
     std::vector<int64_t> cum_work(p.nsets + 1, 0);
-    for (int s = 0; s < p.nsets; ++s) {
-        work += p.sets[s].nstages * tile_cost;
-        cum_work[s + 1] = work;
+    for (int i = 0; i < p.nsets; ++i) {
+        work += p.sets[p.seq[i]].nstages * tile_cost;
+        cum_work[i + 1] = work;
     }
     int64_t want_groups = std::min<int64_t>(BATCH_GROUPS, p.nsets / BATCH_SETS_PER_GROUP);
     if (const char *e = getenv("CUM_BATCH_GROUPS")) {  // a fixed group count (tests, experiments)
@@ -1991,8 +2000,11 @@ cum_status cum_batch_run(cum_batch *p, const double *const *X_i, double *const *
         p->h_cset[s] = p->csets[s];
         p->h_cset[s].X = X_i[s];
         if (mean && mean[s]) p->h_cset[s].mean = mean[s];
-        p->h_setred[s] = p->setred[s];
-        for (int k = 0; k < nk; ++k) p->h_setred[s].kappa[k] = kappa[(int64_t)s * nk + k];
+    }
+    for (int i = 0; i < p->nsets; ++i) {  // finalisation records in group order
+        const int s = p->seq[i];
+        p->h_setred[i] = p->setred[s];
+        for (int k = 0; k < nk; ++k) p->h_setred[i].kappa[k] = kappa[(int64_t)s * nk + k];
     }
     // order after the caller's stream, run on the plan's stream, order the caller after it
     HIP_TRY(hipEventRecord(p->ready, user));
