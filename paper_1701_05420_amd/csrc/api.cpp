@@ -227,6 +227,8 @@ struct OrderPlan {
     std::vector<int32_t> terms;   // orders >= 7: nterm x 2 (set A with position 0, its complement)
     std::vector<int32_t> tpw;     // their multipliers b^|high positions| (see RedOrder::tpw)
     int nterm = 0;
+    int qe = 0;                   // see RedOrder::qe, RedOrder::cstart
+    int32_t cstart[5] = {0};
     std::vector<uint16_t> smask;  // position sets of 2..d-2 positions, by size then value
     std::vector<int32_t> gmap;    // staged slot -> s | flat << 10
     int32_t mstart[MAXD] = {0};   // first staged slot of each set size m (index m - 2)
@@ -279,6 +281,25 @@ static std::vector<Feat> pad_blocks(const std::vector<Feat> &f, const std::vecto
 
 // Plain packing (full 16-blocks) when the dynamic program would take too long.
 constexpr size_t ALIGN_MAX_FEATURES = 1 << 22;
+
+// Digits per lane of the multi-entry first-position finalisation (orders
+// >= 7): a lane takes the b^qe entries that differ only in their last qe
+// digits, at most 4 of them.  Where the block's sub-blocks are staged in LDS
+// (at b = 2 orders 7 and 8) one work-group of 64 lanes covers a block; where
+// they are read from memory, qe is chosen so that a block still spreads over
+// 256 or more lanes.  Other block sizes keep one entry per thread (qe = 0).
+static int first_position_qe(int b, int d, bool staged) {
+    if (b == 2) return staged ? (d >= 8 ? 2 : 1) : (d >= 10 ? 2 : 1);
+    return (b == 3 || b == 4) ? 1 : 0;
+}
+
+// Group of a first-position term by its set A (holding position 0): which of
+// the last qe positions A holds, as bits (position d-qe+i -> bit qe-1-i).
+static int term_group(int mask, int d, int qe) {
+    int c = 0;
+    for (int i = 0; i < qe; ++i) c = c * 2 + (mask >> (d - qe + i) & 1);
+    return c;
+}
 
 static cum_status build_order(int n, int b, int d, OrderPlan &o) {
     o.n = n;
@@ -465,16 +486,27 @@ static cum_status build_order(int n, int b, int d, OrderPlan &o) {
     // M_(d-|A|) of the complement (sets of one position drop out: kappa_1 = 0
     // and central M_1 = 0).  2^(d-1) - d - 1 terms of two factors, against
     // 162, 715, 3425 and 17722 partitions at d = 7..10.
+    // The terms are grouped by which of the last qe positions A holds (see
+    // term_group), so that a thread that takes the b^qe entries sharing all
+    // other digits reads each factor's values for all of them as one run.
     if (d >= FIRST_POSITION_MIN_D) {
         const int full = (1 << d) - 1;
+        o.qe = first_position_qe(b, d, o.lds_elems > 0);
+        std::vector<int> group[5];
         for (int mask = 1; mask < (1 << d); mask += 2) {
             const int m = __builtin_popcount(mask);
             if (m < 2 || m > d - 2) continue;
-            const int comp = full ^ mask;
-            for (int f : {mask, comp}) {
-                const int where = o.lds_elems ? (int)soff[(size_t)sidx[f]] : sidx[f];
-                o.terms.push_back((int32_t)f | (int32_t)(where << 10));
-                o.tpw.push_back((int32_t)ipow64(b, __builtin_popcount((unsigned)f >> ((d + 1) / 2))));
+            group[term_group(mask, d, o.qe)].push_back(mask);
+        }
+        for (int c = 0; c < 5; ++c) {
+            o.cstart[c] = (int32_t)(o.terms.size() / 2);
+            for (int mask : group[c]) {
+                const int comp = full ^ mask;
+                for (int f : {mask, comp}) {
+                    const int where = o.lds_elems ? (int)soff[(size_t)sidx[f]] : sidx[f];
+                    o.terms.push_back((int32_t)f | (int32_t)(where << 10));
+                    o.tpw.push_back((int32_t)ipow64(b, __builtin_popcount((unsigned)f >> ((d + 1) / 2))));
+                }
             }
         }
         o.nterm = (int)o.terms.size() / 2;
@@ -591,6 +623,8 @@ static RedOrder red_order(const OrderPlan &o, const OrderPlan &po, int64_t poff)
     ro.terms = (const int32_t *)o.terms_d.p;
     ro.tpw = (const int32_t *)o.tpw_d.p;
     ro.nterm = o.nterm;
+    ro.qe = o.qe;
+    for (int c = 0; c < 5; ++c) ro.cstart[c] = o.cstart[c];
     ro.prank = (const int64_t *)po.prank_d.p;
     ro.ns = (int32_t)o.smask.size();
     ro.lds_elems = o.lds_elems;
@@ -866,6 +900,21 @@ static cum_status check_prec(int prec) {
 // in FP64 whatever precision was asked for.
 static int staged_prec(int prec, int d_max) { return d_max >= HIGH_F64_MIN_D ? (int)CUM_F64 : prec; }
 
+// Entries per lane of the finalisation of order ro in a launch with
+// arguments ra: b^qe where the first-position formula runs in its
+// multi-entry form, else 1.
+static int32_t gather_entries(const RedOrder &ro, const RedArgs &ra) {
+    if (!ra.recursion || !ra.subset || ro.d < FIRST_POSITION_MIN_D || ro.nterm == 0 || ro.qe <= 0) return 1;
+    return (int32_t)ipow64(ro.b, ro.qe);
+}
+
+// q0, q1 and the staging bits of a launch of orders ro[0 .. ra.nords-1]
+static void set_gather(const RedOrder *ro, RedArgs &ra) {
+    ra.q0 = gather_entries(ro[0], ra);
+    ra.q1 = ra.nords == 2 ? gather_entries(ro[1], ra) : 1;
+    ra.gstaged = (ro[0].lds_elems > 0 ? 1 : 0) | (ra.nords == 2 && ro[1].lds_elems > 0 ? 2 : 0);
+}
+
 // Dynamic LDS of a finalisation launch over orders ro[0..nords-1]: the
 // staged sub-blocks, the block's lower-order offsets and, when everything
 // fits in 64 KiB, the partition table.  Fills the layout fields of ra and
@@ -968,6 +1017,7 @@ static cum_status run_finalize(CallPlan *c, double *sums, int64_t nchunks, int64
             ra.nords = 1;
             ra.nbtot = ra.nb0;
         }
+        set_gather(&c->red[i0], ra);
         const int lds = red_lds_layout(&c->red[i0], ra.nords, recursion, ra);
         const int be0 = (int)ipow64(c->red[i0].b, d);
         HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] { return launch_reduce(ra, 1, lds, be0, s); }));
@@ -1346,6 +1396,18 @@ cum_status cum_plan_check(int n, int d, int b) {
             if (!(masks2[0] & 1) || (masks2[0] ^ masks2[1]) != (1 << d) - 1 || (masks2[0] & masks2[1]))
                 return fail(CUM_EINVAL, "d=%d: term %d is not a set with position 0 and its complement", d, z);
             if (!seen_a.insert(masks2[0]).second) return fail(CUM_EINVAL, "d=%d: term %d repeated", d, z);
+            // the term lies in the group of the last qe positions its set A holds
+            const int grp = term_group(masks2[0], d, o.qe);
+            if (z < o.cstart[grp] || z >= o.cstart[grp + 1])
+                return fail(CUM_EINVAL, "d=%d: term %d outside its group %d", d, z, grp);
+        }
+        if (d >= FIRST_POSITION_MIN_D) {
+            // groups 0 .. 2^qe - 1 in order, the rest empty
+            if (o.qe != first_position_qe(b, d, o.lds_elems > 0) || o.cstart[0] != 0 || o.cstart[1 << o.qe] != o.nterm ||
+                o.cstart[4] != o.nterm)
+                return fail(CUM_EINVAL, "d=%d: term groups", d);
+            for (int c = 0; c < 4; ++c)
+                if (o.cstart[c] > o.cstart[c + 1]) return fail(CUM_EINVAL, "d=%d: term group %d bounds", d, c);
         }
         // staged slots: each set's sub-block in order, grouped by set size
         if (o.lds_elems) {
@@ -1864,6 +1926,7 @@ static cum_status batch_enqueue(cum_batch &p, hipStream_t s) {
             ra.nb0 = p.red[o0].nblocks;
             ra.nbtot = ra.nb0 + (ra.nords == 2 ? p.red[o0 + 1].nblocks : 0);
             ra.sets = setred + s0;
+            set_gather(&p.red[o0], ra);
             const int lds = red_lds_layout(&p.red[o0], ra.nords, true, ra);
             HIP_TRY(launch_reduce(ra, ns, lds, (int)ipow64(p.b, d), fs));
         }

@@ -844,9 +844,30 @@ __device__ __forceinline__ double *mom_of(const SetRed &sr, int m) {
     }
 }
 
-template <int D, int NT, int EPT>
+// Index, in the run of b^|last positions in the set| consecutive values a
+// factor holds for a thread's entries, of entry q's value (the thread's
+// entries differ in their last E digits, q = those digits in base BB).  The
+// term group C has bit E-1-i set when the set A holds position D-E+i; the
+// side is A's (A_SIDE) or its complement's.
+template <unsigned BB, int E, int C, bool A_SIDE>
+__device__ constexpr unsigned run_index(unsigned q) {
+    unsigned j = 0;
+    for (int i = 0; i < E; ++i) {
+        if ((((C >> (E - 1 - i)) & 1) != 0) != A_SIDE) continue;
+        unsigned dig = q;
+        for (int k = 0; k < E - 1 - i; ++k) dig /= BB;
+        j = j * BB + dig % BB;
+    }
+    return j;
+}
+
+// GB > 0: the multi-entry form of the first-position formula with block
+// size GB, GE digits per lane, factors read from the LDS-staged sub-blocks
+// (GST) or from memory (a kernel of its own, see below).
+template <int D, int NT, int EPT, int GB = 0, int GE = 0, bool GST = false>
 __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder &ro, const SetRed &sr, int64_t B,
-                                               int slice, int nslice, char *dyn, int *tup) {
+                                               int slice, int nslice, char *dyn, int *tup, double *gred = nullptr,
+                                               const unsigned char *ptab = nullptr) {
     constexpr int PARTS = D / 2;  // parts per partition slot
     const int tid = threadIdx.x;
     const unsigned b = (unsigned)ro.b;
@@ -903,10 +924,25 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
         __syncthreads();
     }
     if (staged) {
-        // the block's lower-order sub-blocks into LDS
-        for (int e = tid; e < ro.lds_elems; e += NT) {
-            const int g = gmem(ro.gmap)[e];
-            sub[e] = gmem(base[g & 1023])[g >> 10];
+        // the block's lower-order sub-blocks into LDS, eight slots per thread
+        // at a time so that their loads are in flight together
+        // (slots past the end repeat the last one, so that no load is
+        // conditional; only the stores are)
+        const CUM_GLOBAL int32_t *gm = gmem(ro.gmap);
+        const int le = ro.lds_elems;
+        for (int e0 = tid; e0 < le; e0 += 8 * NT) {
+            int g[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) g[i] = gm[min(e0 + i * NT, le - 1)];
+            const double *bp[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bp[i] = base[g[i] & 1023];
+            double v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = gmem(bp[i])[g[i] >> 10];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (e0 + i * NT < le) sub[e0 + i * NT] = v[i];
         }
         __syncthreads();
     }
@@ -923,263 +959,457 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
 #pragma unroll
     for (int k = 0; k + 1 < D; ++k) need_sort |= tup[k] == tup[k + 1];
 
-    for (unsigned o0 = (unsigned)(slice * NT * EPT + tid); o0 < be; o0 += (unsigned)(NT * EPT * nslice)) {
-        int r[EPT][D];  // in-block digits, first position most significant
-        double M[EPT];
+    // M = S / t of the entry with in-block index oo and digits rr, from the
+    // partial sums (0 for an entry past the block's end)
+    auto moment_at = [&](const int (&rr)[D], unsigned oo, bool valid) -> double {
+        int64_t poff = (int64_t)B * be + oo;
+        bool pad = !valid;
+        if (canon && valid) {
+            int u[D];
 #pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            unsigned oo = o0 + (unsigned)NT * q;
-            const bool valid = oo < be;
-            if (!valid) oo = 0;
+            for (int k = 0; k < D; ++k) u[k] = tup[k] * ro.b + rr[k];
+            if (need_sort) {
+                // odd-even transposition network: D rounds sort D keys
 #pragma unroll
-            for (int k = D - 1; k >= 0; --k) {
-                r[q][k] = (int)(oo % b);
-                oo /= b;
-            }
-            int64_t poff = (int64_t)B * be + o0 + (unsigned)NT * q;
-            bool pad = !valid;
-            if (canon && valid) {
-                int u[D];
+                for (int rd = 0; rd < D; ++rd)
 #pragma unroll
-                for (int k = 0; k < D; ++k) u[k] = tup[k] * ro.b + r[q][k];
-                if (need_sort) {
-                    // odd-even transposition network: D rounds sort D keys
-#pragma unroll
-                    for (int rd = 0; rd < D; ++rd)
-#pragma unroll
-                        for (int k = rd & 1; k + 1 < D; k += 2) {
-                            const int lo = min(u[k], u[k + 1]), hi = max(u[k], u[k + 1]);
-                            u[k] = lo;
-                            u[k + 1] = hi;
-                        }
-                }
-                int umax = 0;
-#pragma unroll
-                for (int k = 0; k < D; ++k) umax = max(umax, u[k]);
-                pad = umax >= ro.n;  // a padded position of a ragged block: M = 0
-                if (!pad) {
-                    const int pb = ro.pb, w = ro.pnbar + 1;
-                    int64_t rank = 0, in = 0;
-                    int prev = 0;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        const int jb = pb == 1 ? u[k] : u[k] / pb;
-                        rank += prank[k * w + prev] - prank[k * w + jb];
-                        in = in * pb + (u[k] - jb * pb);
-                        prev = jb;
+                    for (int k = rd & 1; k + 1 < D; k += 2) {
+                        const int lo = min(u[k], u[k + 1]), hi = max(u[k], u[k + 1]);
+                        u[k] = lo;
+                        u[k + 1] = hi;
                     }
-                    poff = rank + in;
-                }
             }
-            double S = 0.0;
+            int umax = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) umax = max(umax, u[k]);
+            pad = umax >= ro.n;  // a padded position of a ragged block: M = 0
             if (!pad) {
-                const CUM_GLOBAL double *pp = partial + poff;
-                int64_t c = 0;
-                // eight independent loads in flight, summed in chunk order
-                for (; c + 8 <= nchunks; c += 8) {
-                    double v[8];
+                const int pb = ro.pb, w = ro.pnbar + 1;
+                int64_t rank = 0, in = 0;
+                int prev = 0;
 #pragma unroll
-                    for (int x = 0; x < 8; ++x) v[x] = pp[(c + x) * stride];
-#pragma unroll
-                    for (int x = 0; x < 8; ++x) S += v[x];
+                for (int k = 0; k < D; ++k) {
+                    const int jb = pb == 1 ? u[k] : u[k] / pb;
+                    rank += prank[k * w + prev] - prank[k * w + jb];
+                    in = in * pb + (u[k] - jb * pb);
+                    prev = jb;
                 }
-                for (; c < nchunks; ++c) S += pp[c * stride];
-            }
-            M[q] = S / tt;
-        }
-        // One entry per thread: the in-block index of the entry's digits at
-        // the positions of any set, from two tables built once per entry.
-        // Positions 0..HL-1 index tlo, positions HL..D-1 index thi (by the set
-        // mask shifted down by HL); each table entry follows from the one
-        // without its last position by one step of Horner's rule, and a set's
-        // index is tlo[low part] * b^|high part| + thi[high part].
-        constexpr int HL = (D + 1) / 2, HH = D - HL;
-        unsigned tlo[1 << HL], thi[1 << HH];
-        const unsigned b2 = b * b, b4 = b2 * b2;  // b^|high part| = b^(c&1) b2^(c>>1&1) b4^(c>>2), c <= 5
-        if constexpr (EPT == 1) {
-            tlo[0] = 0;
-#pragma unroll
-            for (int m = 1; m < (1 << HL); ++m) {
-                const int k = 31 - __builtin_clz((unsigned)m);
-                tlo[m] = __umul24(tlo[m & ~(1 << k)], b) + (unsigned)r[0][k];
-            }
-            thi[0] = 0;
-#pragma unroll
-            for (int m = 1; m < (1 << HH); ++m) {
-                const int k = 31 - __builtin_clz((unsigned)m);
-                thi[m] = __umul24(thi[m & ~(1 << k)], b) + (unsigned)r[0][HL + k];
+                poff = rank + in;
             }
         }
-        // One factor of a term for every entry of the thread: the lower-order
-        // sub-block of part pk (position mask | where << 10), read in LDS
-        // (staged) or in memory, where first-position formula factors without
-        // position 0 are central moments.  The part is the same for every lane:
-        // readfirstlane makes that explicit, so that the position tests are
-        // scalar.
-        // pw0: the set's multiplier b^|high part| when the table gives it (the
-        // first-position terms), else negative
-        auto factor = [&](auto staged_t, int pk0, double (&v)[EPT], int pw0 = -1) {
-            constexpr bool ST = decltype(staged_t)::value;
-            const int pk = __builtin_amdgcn_readfirstlane(pk0);
-            const unsigned mask = (unsigned)pk & 1023u;
-            const int where = pk >> 10;
-            if constexpr (EPT == 1) {
-                const unsigned lo = mask & ((1u << HL) - 1u), hi = mask >> HL;
-                unsigned pw;
-                if (pw0 >= 0) {
-                    pw = (unsigned)__builtin_amdgcn_readfirstlane(pw0);
-                } else {
-                    const unsigned c = __builtin_popcount(hi);
-                    pw = ((c & 1u) ? b : 1u) * ((c & 2u) ? b2 : 1u) * ((c & 4u) ? b4 : 1u);
-                }
-                const unsigned flat = __umul24(tlo[lo], pw) + thi[hi];
-                if constexpr (ST)
-                    v[0] = sub[where + flat];
-                else
-                    v[0] = gmem(base[where])[flat];
-                return;
+        double S = 0.0;
+        if (!pad) {
+            const CUM_GLOBAL double *pp = partial + poff;
+            int64_t c = 0;
+            // eight independent loads in flight, summed in chunk order
+            for (; c + 8 <= nchunks; c += 8) {
+                double v[8];
+#pragma unroll
+                for (int x = 0; x < 8; ++x) v[x] = pp[(c + x) * stride];
+#pragma unroll
+                for (int x = 0; x < 8; ++x) S += v[x];
             }
-            // In-block index of the sub-block entry, by Horner's rule over the
-            // digits of the set's positions.  A set has at most D - 2
-            // positions, so every product below is of a value under b^(D-3)
-            // by b; with blocks under 2^31 entries (b^D < 2^31, D <= 10)
-            // b^(D-3) stays under 2^24, and the 24-bit multiply-add, a full
-            // rate vector instruction, is exact.
+            for (; c < nchunks; ++c) S += pp[c * stride];
+        }
+        return S / tt;
+    };
+
+    // Orders >= 7 in the multi-entry form (launched on their own, GB = b):
+    // the first-position formula with factors read from the staged
+    // sub-blocks in LDS (GST) or from memory.  Each lane takes the BB^E
+    // entries that differ only in their last E digits: a factor's values for
+    // them are one run of consecutive values of its sub-block (its digits on
+    // the last E positions are the least significant), a single value when
+    // the set holds none of those positions.  The terms come grouped by which of them A holds, so each
+    // group's run lengths are known at compile time.  The four waves of the
+    // work-group take the same 64 lanes' entries and a quarter of the terms
+    // each; wave 0 adds the other waves' sums to its own, in wave order.
+    if constexpr (GB > 0) {
+        auto gather_multi = [&](auto b_t, auto e_t) {
+            constexpr unsigned BB = decltype(b_t)::value;
+            constexpr int E = decltype(e_t)::value;
+            constexpr unsigned Q = E == 2 ? BB * BB : BB;
+            constexpr int DP = D - E;  // digits of the lane's entry group u
+            constexpr int HL = (DP + 1) / 2, HH = DP - HL;
+            constexpr int TW = NT / 64;  // waves sharing the terms
+            static_assert(Q <= 4 && TW >= 1, "gathering layout");
+            const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+            const CUM_CONST int32_t *terms_c = cmem(ro.terms);
+            CUM_GLOBAL double *out_m = gmem(sr.kappa[D - 2]);
+            CUM_GLOBAL double *mo = sr.mom[D - 2] ? gmem(sr.mom[D - 2]) : nullptr;
+            const unsigned bu = be / Q;
+            const int zlo = (int)((int64_t)ro.nterm * wave / TW), zhi = (int)((int64_t)ro.nterm * (wave + 1) / TW);
+            // the loop bounds are the same in every lane (barriers inside)
+            for (unsigned u0 = (unsigned)slice * 64u; u0 < bu; u0 += 64u * (unsigned)nslice) {
+                const bool valid = u0 + (unsigned)lane < bu;
+                const unsigned u = valid ? u0 + (unsigned)lane : u0;
+                int rr[D];
+                unsigned x = u;
+#pragma unroll
+                for (int k = DP - 1; k >= 0; --k) {
+                    rr[k] = (int)(x % BB);
+                    x /= BB;
+                }
+                // index of u's digits at the positions of any set: for b = 2
+                // a bit extraction (below), else from two tables over
+                // positions 0..HL-1 and HL..DP-1 (as in the one-entry form)
+                constexpr bool BITS = BB == 2;
+                constexpr int TL = BITS ? 1 : (1 << HL), TH = BITS ? 1 : (1 << HH);
+                unsigned tlo[TL], thi[TH];
+                tlo[0] = thi[0] = 0;
+                if constexpr (!BITS) {
+#pragma unroll
+                    for (int m = 1; m < TL; ++m) {
+                        const int k = 31 - __builtin_clz((unsigned)m);
+                        tlo[m] = tlo[m & ~(1 << k)] * BB + (unsigned)rr[k];
+                    }
+#pragma unroll
+                    for (int m = 1; m < TH; ++m) {
+                        const int k = 31 - __builtin_clz((unsigned)m);
+                        thi[m] = thi[m & ~(1 << k)] * BB + (unsigned)rr[HL + k];
+                    }
+                }
+                // b = 2: u's bit DP-1-k is the digit of position k, and its low
+                // six bits are the lane; the wave's high bits are uniform
+                const unsigned uh = u0 >> 6;
+                double sum[Q];
+#pragma unroll
+                for (unsigned q = 0; q < Q; ++q) sum[q] = 0.0;
+                // the N values of factor pk (mask | set index << 10) for the
+                // lane's entries
+                auto load = [&](int pk0, auto n_t, double *v) {
+                    constexpr unsigned N = decltype(n_t)::value;
+                    const int pk = __builtin_amdgcn_readfirstlane(pk0);
+                    const unsigned mask = (unsigned)pk & 1023u;
+                    unsigned flat;
+                    if constexpr (BITS) {
+                        // the set's bits of u, in u's order: the uniform high
+                        // part, then the lane's six bits from the table
+                        static_assert(DP >= 6 && DP <= 8, "bit layout");
+                        const unsigned rm = __builtin_bitreverse32(mask & ((1u << DP) - 1u)) >> (32 - DP);
+                        const unsigned ml = rm & 63u, mh = rm >> 6;
+                        unsigned hp = 0, k = 0;
+#pragma unroll
+                        for (int i = 0; i < DP - 6; ++i)
+                            if (mh >> i & 1u) hp |= ((uh >> i) & 1u) << k++;
+                        flat = ((hp << __builtin_popcount(ml)) | ptab[ml * 64 + lane]) * N;
+                    } else {
+                        const unsigned lo = mask & ((1u << HL) - 1u), hi = (mask >> HL) & ((1u << HH) - 1u);
+                        const unsigned c = __builtin_popcount(hi);
+                        unsigned pw = 1;
+                        for (unsigned i = 0; i < c; ++i) pw *= BB;
+                        flat = (tlo[lo] * pw + thi[hi]) * N;
+                    }
+                    if constexpr (GST) {
+                        const double *p = sub + (pk >> 10) + flat;
+#pragma unroll
+                        for (unsigned j = 0; j < N; ++j) v[j] = p[j];
+                    } else {
+                        const CUM_GLOBAL double *p = gmem(base[pk >> 10]) + flat;
+#pragma unroll
+                        for (unsigned j = 0; j < N; ++j) v[j] = p[j];
+                    }
+                };
+                auto group = [&](auto c_t) {
+                    constexpr int C = decltype(c_t)::value;
+                    constexpr int KA = (C & 1) + ((C >> 1) & 1);  // last positions A holds
+                    constexpr unsigned NA = KA == 0 ? 1u : (KA == 1 ? BB : BB * BB), NC = Q / NA;
+                    const int z1 = min(ro.cstart[C + 1], zhi);
+                    int z = max(ro.cstart[C], zlo);
+                    // four terms' factors in flight at once (eight need more registers
+                    // than three waves per SIMD allow)
+                    for (; z + 4 <= z1; z += 4) {
+                        int pk[8];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) pk[i] = terms_c[z * 2 + i];
+                        double va[4][NA], vc[4][NC];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            load(pk[2 * i], std::integral_constant<unsigned, NA>(), va[i]);
+                            load(pk[2 * i + 1], std::integral_constant<unsigned, NC>(), vc[i]);
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (unsigned q = 0; q < Q; ++q)
+                                sum[q] += va[i][run_index<BB, E, C, true>(q)] * vc[i][run_index<BB, E, C, false>(q)];
+                    }
+                    for (; z < z1; ++z) {
+                        double va[NA], vc[NC];
+                        load(terms_c[z * 2], std::integral_constant<unsigned, NA>(), va);
+                        load(terms_c[z * 2 + 1], std::integral_constant<unsigned, NC>(), vc);
+#pragma unroll
+                        for (unsigned q = 0; q < Q; ++q)
+                            sum[q] += va[run_index<BB, E, C, true>(q)] * vc[run_index<BB, E, C, false>(q)];
+                    }
+                };
+                group(std::integral_constant<int, 0>());
+                group(std::integral_constant<int, 1>());
+                if constexpr (E == 2) {
+                    group(std::integral_constant<int, 2>());
+                    group(std::integral_constant<int, 3>());
+                }
+                // the other waves' sums go to LDS: into the staged sub-blocks
+                // once every wave is done reading them, else into gred
+                double *gr = gred;
+                if constexpr (GST) {
+                    __syncthreads();
+                    gr = sub;
+                }
+                if (wave > 0) {
+#pragma unroll
+                    for (unsigned q = 0; q < Q; ++q) gr[((wave - 1) * 4 + (int)q) * 64 + lane] = sum[q];
+                }
+                // the moments after the terms, so that their registers are
+                // free during the term loop
+                double M[Q];
+                if (wave == 0) {
+                    x = u;
+#pragma unroll
+                    for (int k = DP - 1; k >= 0; --k) {
+                        rr[k] = (int)(x % BB);
+                        x /= BB;
+                    }
+#pragma unroll
+                    for (unsigned q = 0; q < Q; ++q) {
+                        unsigned y = q;
+#pragma unroll
+                        for (int k = D - 1; k >= DP; --k) {
+                            rr[k] = (int)(y % BB);
+                            y /= BB;
+                        }
+                        M[q] = moment_at(rr, u * Q + q, valid);
+                    }
+                }
+                __syncthreads();
+                if (wave == 0 && valid) {
+                    const int64_t e0 = (int64_t)B * be + (int64_t)u * Q;
+#pragma unroll
+                    for (unsigned q = 0; q < Q; ++q) {
+                        double sq = sum[q];
+                        for (int w = 1; w < TW; ++w) sq += gr[((w - 1) * 4 + (int)q) * 64 + lane];
+                        if (mo) mo[e0 + q] = M[q];
+                        out_m[e0 + q] = M[q] - sq;
+                    }
+                }
+                __syncthreads();  // gr is free again
+            }
+        };
+        // (the host launches this kernel only for b = GB, qe = GE)
+        gather_multi(std::integral_constant<unsigned, (unsigned)GB>(), std::integral_constant<int, GE>());
+        if (sr.stamp && tid == 0) atomicMax(sr.stamp, (unsigned long long)wall_clock64());
+        return;
+    } else {
+        for (unsigned o0 = (unsigned)(slice * NT * EPT + tid); o0 < be; o0 += (unsigned)(NT * EPT * nslice)) {
+            int r[EPT][D];  // in-block digits, first position most significant
+            double M[EPT];
 #pragma unroll
             for (int q = 0; q < EPT; ++q) {
-                unsigned flat = 0;
+                unsigned oo = o0 + (unsigned)NT * q;
+                const bool valid = oo < be;
+                if (!valid) oo = 0;
+                unsigned x = oo;
 #pragma unroll
-                for (int k = 0; k < D; ++k)
-                    if (mask >> k & 1u) flat = __umul24(flat, b) + (unsigned)r[q][k];
-                if constexpr (ST)
-                    v[q] = sub[where + flat];
-                else
-                    v[q] = gmem(base[where])[flat];
+                for (int k = D - 1; k >= 0; --k) {
+                    r[q][k] = (int)(x % b);
+                    x /= b;
+                }
+                M[q] = moment_at(r[q], oo, valid);
             }
-        };
-        auto part_at = [&](const CUM_CONST int32_t *table, int i) {
-            return __builtin_amdgcn_readfirstlane(parts_in_lds ? parts_l[i] : table[i]);
-        };
-        // the first-position formula: sum over sets A holding position 0 of
-        // kappa(A) times the central moment of the complement, in term order
-        auto first_position = [&](auto staged_t) {
-            double sum[EPT];
-#pragma unroll
-            for (int q = 0; q < EPT; ++q) sum[q] = 0.0;
-            int z = 0;
+            // One entry per thread: the in-block index of the entry's digits at
+            // the positions of any set, from two tables built once per entry.
+            // Positions 0..HL-1 index tlo, positions HL..D-1 index thi (by the set
+            // mask shifted down by HL); each table entry follows from the one
+            // without its last position by one step of Horner's rule, and a set's
+            // index is tlo[low part] * b^|high part| + thi[high part].
+            constexpr int HL = (D + 1) / 2, HH = D - HL;
+            unsigned tlo[1 << HL], thi[1 << HH];
+            const unsigned b2 = b * b, b4 = b2 * b2;  // b^|high part| = b^(c&1) b2^(c>>1&1) b4^(c>>2), c <= 5
             if constexpr (EPT == 1) {
-                // one entry per thread: eight terms' parts in one scalar read,
-                // then their sixteen loads in flight at once
-                for (; z + 8 <= ro.nterm; z += 8) {
-                    int pk[16], pw[16];
+                tlo[0] = 0;
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) pk[i] = terms_g[z * 2 + i];
+                for (int m = 1; m < (1 << HL); ++m) {
+                    const int k = 31 - __builtin_clz((unsigned)m);
+                    tlo[m] = __umul24(tlo[m & ~(1 << k)], b) + (unsigned)r[0][k];
+                }
+                thi[0] = 0;
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) pw[i] = tpw_g[z * 2 + i];
-                    double v[16][EPT];
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) factor(staged_t, pk[i], v[i], pw[i]);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) sum[0] += v[2 * u][0] * v[2 * u + 1][0];
+                for (int m = 1; m < (1 << HH); ++m) {
+                    const int k = 31 - __builtin_clz((unsigned)m);
+                    thi[m] = __umul24(thi[m & ~(1 << k)], b) + (unsigned)r[0][HL + k];
                 }
             }
-            for (; z < ro.nterm; ++z) {
-                double v0[EPT], v1[EPT];
-                factor(staged_t, part_at(terms_g, z * 2), v0);
-                factor(staged_t, part_at(terms_g, z * 2 + 1), v1);
+            // One factor of a term for every entry of the thread: the lower-order
+            // sub-block of part pk (position mask | where << 10), read in LDS
+            // (staged) or in memory, where first-position formula factors without
+            // position 0 are central moments.  The part is the same for every lane:
+            // readfirstlane makes that explicit, so that the position tests are
+            // scalar.
+            // pw0: the set's multiplier b^|high part| when the table gives it (the
+            // first-position terms), else negative
+            auto factor = [&](auto staged_t, int pk0, double (&v)[EPT], int pw0 = -1) {
+                constexpr bool ST = decltype(staged_t)::value;
+                const int pk = __builtin_amdgcn_readfirstlane(pk0);
+                const unsigned mask = (unsigned)pk & 1023u;
+                const int where = pk >> 10;
+                if constexpr (EPT == 1) {
+                    const unsigned lo = mask & ((1u << HL) - 1u), hi = mask >> HL;
+                    unsigned pw;
+                    if (pw0 >= 0) {
+                        pw = (unsigned)__builtin_amdgcn_readfirstlane(pw0);
+                    } else {
+                        const unsigned c = __builtin_popcount(hi);
+                        pw = ((c & 1u) ? b : 1u) * ((c & 2u) ? b2 : 1u) * ((c & 4u) ? b4 : 1u);
+                    }
+                    const unsigned flat = __umul24(tlo[lo], pw) + thi[hi];
+                    if constexpr (ST)
+                        v[0] = sub[where + flat];
+                    else
+                        v[0] = gmem(base[where])[flat];
+                    return;
+                }
+                // In-block index of the sub-block entry, by Horner's rule over the
+                // digits of the set's positions.  A set has at most D - 2
+                // positions, so every product below is of a value under b^(D-3)
+                // by b; with blocks under 2^31 entries (b^D < 2^31, D <= 10)
+                // b^(D-3) stays under 2^24, and the 24-bit multiply-add, a full
+                // rate vector instruction, is exact.
 #pragma unroll
-                for (int q = 0; q < EPT; ++q) sum[q] += v0[q] * v1[q];
-            }
+                for (int q = 0; q < EPT; ++q) {
+                    unsigned flat = 0;
 #pragma unroll
-            for (int q = 0; q < EPT; ++q) M[q] -= sum[q];
-        };
-        // sum over partitions of products of lower cumulants, in partition
-        // order; a partition's row ends at its first zero part
-        auto recursion = [&](auto staged_t) {
-            double sum[EPT];
+                    for (int k = 0; k < D; ++k)
+                        if (mask >> k & 1u) flat = __umul24(flat, b) + (unsigned)r[q][k];
+                    if constexpr (ST)
+                        v[q] = sub[where + flat];
+                    else
+                        v[q] = gmem(base[where])[flat];
+                }
+            };
+            auto part_at = [&](const CUM_CONST int32_t *table, int i) {
+                return __builtin_amdgcn_readfirstlane(parts_in_lds ? parts_l[i] : table[i]);
+            };
+            // the first-position formula: sum over sets A holding position 0 of
+            // kappa(A) times the central moment of the complement, in term order
+            auto first_position = [&](auto staged_t) {
+                double sum[EPT];
 #pragma unroll
-            for (int q = 0; q < EPT; ++q) sum[q] = 0.0;
-            int z = 0;
-            if constexpr (EPT == 1) {
-                for (; z + 4 <= ro.npart; z += 4) {
-                    int pks[4 * PARTS];
+                for (int q = 0; q < EPT; ++q) sum[q] = 0.0;
+                int z = 0;
+                if constexpr (EPT == 1) {
+                    // one entry per thread: eight terms' parts in one scalar read,
+                    // then their sixteen loads in flight at once
+                    for (; z + 8 <= ro.nterm; z += 8) {
+                        int pk[16], pw[16];
 #pragma unroll
-                    for (int i = 0; i < 4 * PARTS; ++i) pks[i] = parts_g[z * PARTS + i];
-                    double prod[4];
+                        for (int i = 0; i < 16; ++i) pk[i] = terms_g[z * 2 + i];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        double v[PARTS][EPT];
-                        bool live = true;
+                        for (int i = 0; i < 16; ++i) pw[i] = tpw_g[z * 2 + i];
+                        double v[16][EPT];
 #pragma unroll
-                        for (int pt = 0; pt < PARTS; ++pt) {
-                            const int pk = __builtin_amdgcn_readfirstlane(pks[u * PARTS + pt]);
-                            live = live && pk != 0;
-                            if (live)
-                                factor(staged_t, pk, v[pt]);
-                            else
-                                v[pt][0] = 1.0;
+                        for (int i = 0; i < 16; ++i) factor(staged_t, pk[i], v[i], pw[i]);
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) sum[0] += v[2 * u][0] * v[2 * u + 1][0];
+                    }
+                }
+                for (; z < ro.nterm; ++z) {
+                    double v0[EPT], v1[EPT];
+                    factor(staged_t, part_at(terms_g, z * 2), v0);
+                    factor(staged_t, part_at(terms_g, z * 2 + 1), v1);
+#pragma unroll
+                    for (int q = 0; q < EPT; ++q) sum[q] += v0[q] * v1[q];
+                }
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) M[q] -= sum[q];
+            };
+            // sum over partitions of products of lower cumulants, in partition
+            // order; a partition's row ends at its first zero part
+            auto recursion = [&](auto staged_t) {
+                double sum[EPT];
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) sum[q] = 0.0;
+                int z = 0;
+                if constexpr (EPT == 1) {
+                    for (; z + 4 <= ro.npart; z += 4) {
+                        int pks[4 * PARTS];
+#pragma unroll
+                        for (int i = 0; i < 4 * PARTS; ++i) pks[i] = parts_g[z * PARTS + i];
+                        double prod[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            double v[PARTS][EPT];
+                            bool live = true;
+#pragma unroll
+                            for (int pt = 0; pt < PARTS; ++pt) {
+                                const int pk = __builtin_amdgcn_readfirstlane(pks[u * PARTS + pt]);
+                                live = live && pk != 0;
+                                if (live)
+                                    factor(staged_t, pk, v[pt]);
+                                else
+                                    v[pt][0] = 1.0;
+                            }
+                            prod[u] = 1.0;
+#pragma unroll
+                            for (int pt = 0; pt < PARTS; ++pt) prod[u] *= v[pt][0];
                         }
-                        prod[u] = 1.0;
 #pragma unroll
-                        for (int pt = 0; pt < PARTS; ++pt) prod[u] *= v[pt][0];
+                        for (int u = 0; u < 4; ++u) sum[0] += prod[u];
+                    }
+                }
+                for (; z < ro.npart; ++z) {
+                    double prod[EPT];
+#pragma unroll
+                    for (int q = 0; q < EPT; ++q) prod[q] = 1.0;
+#pragma unroll
+                    for (int pt = 0; pt < PARTS; ++pt) {
+                        const int pk = part_at(parts_g, z * PARTS + pt);
+                        if (!pk) break;
+                        double v[EPT];
+                        factor(staged_t, pk, v);
+#pragma unroll
+                        for (int q = 0; q < EPT; ++q) prod[q] *= v[q];
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) sum[0] += prod[u];
-                }
-            }
-            for (; z < ro.npart; ++z) {
-                double prod[EPT];
-#pragma unroll
-                for (int q = 0; q < EPT; ++q) prod[q] = 1.0;
-#pragma unroll
-                for (int pt = 0; pt < PARTS; ++pt) {
-                    const int pk = part_at(parts_g, z * PARTS + pt);
-                    if (!pk) break;
-                    double v[EPT];
-                    factor(staged_t, pk, v);
-#pragma unroll
-                    for (int q = 0; q < EPT; ++q) prod[q] *= v[q];
+                    for (int q = 0; q < EPT; ++q) sum[q] += prod[q];
                 }
 #pragma unroll
-                for (int q = 0; q < EPT; ++q) sum[q] += prod[q];
-            }
+                for (int q = 0; q < EPT; ++q) M[q] -= sum[q];
+            };
+            // the central moments of this order, for the first-position formula of
+            // higher orders
+            if (sr.mom[D - 2]) {
+                CUM_GLOBAL double *mo = gmem(sr.mom[D - 2]);
 #pragma unroll
-            for (int q = 0; q < EPT; ++q) M[q] -= sum[q];
-        };
-        // the central moments of this order, for the first-position formula of
-        // higher orders
-        if (sr.mom[D - 2]) {
-            CUM_GLOBAL double *mo = gmem(sr.mom[D - 2]);
+                for (int q = 0; q < EPT; ++q) {
+                    const unsigned o = o0 + (unsigned)NT * q;
+                    if (o < be) mo[B * be + o] = M[q];
+                }
+            }
+            if constexpr (D >= FIRST_POSITION_MIN_D) {
+                if (first_pos) {
+                    if (staged)
+                        first_position(std::true_type());
+                    else
+                        first_position(std::false_type());
+                } else if (staged) {
+                    recursion(std::true_type());
+                } else if (rec) {
+                    recursion(std::false_type());
+                }
+            } else {
+                if (staged)
+                    recursion(std::true_type());
+                else if (rec)
+                    recursion(std::false_type());
+            }
 #pragma unroll
             for (int q = 0; q < EPT; ++q) {
                 const unsigned o = o0 + (unsigned)NT * q;
-                if (o < be) mo[B * be + o] = M[q];
+                if (o < be) out[B * be + o] = M[q];
             }
         }
-        if constexpr (D >= FIRST_POSITION_MIN_D) {
-            if (first_pos) {
-                if (staged)
-                    first_position(std::true_type());
-                else
-                    first_position(std::false_type());
-            } else if (staged) {
-                recursion(std::true_type());
-            } else if (rec) {
-                recursion(std::false_type());
-            }
-        } else {
-            if (staged)
-                recursion(std::true_type());
-            else if (rec)
-                recursion(std::false_type());
-        }
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            const unsigned o = o0 + (unsigned)NT * q;
-            if (o < be) out[B * be + o] = M[q];
-        }
+        if (sr.stamp && tid == 0) atomicMax(sr.stamp, (unsigned long long)wall_clock64());
     }
-    if (sr.stamp && tid == 0) atomicMax(sr.stamp, (unsigned long long)wall_clock64());
 }
 
 // NT threads per work-group: 256, or one wave (64) when the blocks are small,
@@ -1204,6 +1434,36 @@ __global__ __launch_bounds__(NT) void reduce_kernel(RedArgs a) {
             }
         }
     }
+}
+
+// One order D in the multi-entry form (block size GB, GE digits per lane,
+// factors in LDS when ST), a kernel of its own so that its registers do not
+// weigh on the other finalisation kernels.
+template <int D, int GB, int GE, bool ST>
+__global__ __launch_bounds__(256) void gather_kernel(RedArgs a) {
+    extern __shared__ __align__(16) char dyn[];
+    __shared__ int tup[MAXD];
+    SetRed sr = a.set0;
+    if (a.sets) sr = a.sets[blockIdx.y];
+    // the sums of waves 1..3, 4 entries per lane (staged launches use the
+    // staged sub-blocks' LDS, which holds at least as much, once read)
+    __shared__ double gred[ST ? 1 : 3 * 4 * 64];
+    // b = 2: ptab[m * 64 + l] = the bits of lane l selected by mask m, packed
+    // in order (made visible by the first barrier of the block loop)
+    __shared__ unsigned char ptab[GB == 2 ? 64 * 64 : 1];
+    if constexpr (GB == 2) {
+        for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+            const unsigned m = (unsigned)i >> 6, l = (unsigned)i & 63u;
+            unsigned r = 0, k = 0;
+            for (int j = 0; j < 6; ++j)
+                if (m >> j & 1u) r |= ((l >> j) & 1u) << k++;
+            ptab[i] = (unsigned char)r;
+        }
+    }
+    const RedOrder ro = a.ords[0];
+    const int64_t ntot = a.nb0 * a.sl0;
+    for (int64_t g = blockIdx.x; g < ntot; g += gridDim.x)
+        finalize_block<D, 256, 1, GB, GE, ST>(a, ro, sr, g / a.sl0, (int)(g % a.sl0), a.sl0, dyn, tup, gred, ptab);
 }
 
 // Sum of the per-chunk partial sums of every entry, in chunk order (Alg. 3's
@@ -1269,13 +1529,68 @@ static void launch_reduce_nt(const RedArgs &a, dim3 grid, int lds_bytes, hipStre
 // terms, and the blocks are few: one entry per thread, and a block's entries
 // over as many work-groups as it fills.  Elsewhere four entries per thread
 // and one work-group per block.
-hipError_t launch_reduce(const RedArgs &a0, int nsets, int lds_bytes, int block_elems, hipStream_t s) {
+// wide_in: -1 to decide from the launch's orders, else the layout of the
+// pair of orders this launch was split from
+static hipError_t launch_reduce_impl(const RedArgs &a0, int nsets, int lds_bytes, int block_elems, int wide_in,
+                                     hipStream_t s) {
     if (a0.d0 < 2 || a0.d0 > MAXD || block_elems < 1) return hipErrorInvalidValue;
     RedArgs a = a0;
     const int top = a.d0 + (a.nords == 2 ? 1 : 0);
-    const bool wide = a.recursion && top >= FIRST_POSITION_MIN_D && a.d0 >= 6;
+    const bool wide = wide_in >= 0 ? wide_in != 0 : (a.recursion && top >= FIRST_POSITION_MIN_D && a.d0 >= 6);
     const int nt = wide ? (block_elems >= 256 ? 256 : 64) : (block_elems <= 64 * RED_EPT ? 64 : 256);
     const int64_t be1 = (int64_t)block_elems * a.b;  // entries per block of order d0 + 1
+    // several entries per lane only in launches whose top order is 7 or more
+    if (!wide || a.q0 < 1) a.q0 = 1;
+    if (!wide || a.q1 < 1) a.q1 = 1;
+    if (a.nords == 2 && (a.q0 > 1 || a.q1 > 1)) {
+        // an order in the multi-entry form is a launch of its own
+        RedArgs a1 = a, a2 = a;
+        a1.nords = 1;
+        a1.nbtot = a1.nb0;
+        a1.q1 = 1;
+        a1.gstaged = a.gstaged & 1;
+        a2.ords = a.ords + 1;
+        a2.nords = 1;
+        a2.d0 = a.d0 + 1;
+        a2.nb0 = a2.nbtot = a.nbtot - a.nb0;
+        a2.q0 = a.q1;
+        a2.q1 = 1;
+        a2.gstaged = (a.gstaged >> 1) & 1;
+        // the other order keeps the pair's one-entry-per-thread layout
+        const hipError_t e = launch_reduce_impl(a1, nsets, lds_bytes, block_elems, wide ? 1 : 0, s);
+        if (e != hipSuccess) return e;
+        return launch_reduce_impl(a2, nsets, lds_bytes, (int)be1, wide ? 1 : 0, s);
+    }
+    if (a.q0 > 1) {
+        // b^qe entries per lane: qe = 2 only for b = 2 (4 entries), else 1;
+        // staged sub-blocks only at b = 2, orders 7 and 8
+        if (block_elems % a.q0) return hipErrorInvalidValue;
+        const int ge = (a.q0 == a.b) ? 1 : (a.b == 2 && a.q0 == 4 ? 2 : 0);
+        const int st = a.gstaged & 1;
+        if (!ge || a.b < 2 || a.b > 4 || a.d0 < FIRST_POSITION_MIN_D) return hipErrorInvalidValue;
+        // a staged launch keeps three waves' sums in its staged sub-blocks' LDS
+        if (st && a.base_off < 3 * 4 * 64 * (int)sizeof(double)) return hipErrorInvalidValue;
+        const int64_t per = 64 * (int64_t)a.q0;  // 64 lanes' entries per work-group
+        a.sl0 = (int32_t)((block_elems + per - 1) / per);
+        int64_t gg = a.nb0 * a.sl0;
+        if (gg > 65535) gg = 65535;
+        if (gg < 1) gg = 1;
+        const dim3 ggrid((unsigned)gg, (unsigned)nsets);
+        const int key = a.d0 * 1000 + a.b * 100 + ge * 10 + st;
+        switch (key) {
+#define CUM_GATHER(D, B, E, ST) \
+    case D * 1000 + B * 100 + E * 10 + ST: \
+        hipLaunchKernelGGL((gather_kernel<D, B, E, ST != 0>), ggrid, dim3(256), (size_t)lds_bytes, s, a); \
+        break;
+            CUM_GATHER(7, 2, 1, 1) CUM_GATHER(8, 2, 2, 1)
+            CUM_GATHER(9, 2, 1, 0) CUM_GATHER(10, 2, 2, 0)
+            CUM_GATHER(7, 3, 1, 0) CUM_GATHER(8, 3, 1, 0) CUM_GATHER(9, 3, 1, 0) CUM_GATHER(10, 3, 1, 0)
+            CUM_GATHER(7, 4, 1, 0) CUM_GATHER(8, 4, 1, 0) CUM_GATHER(9, 4, 1, 0) CUM_GATHER(10, 4, 1, 0)
+#undef CUM_GATHER
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     a.sl0 = wide ? (int32_t)((block_elems + nt - 1) / nt) : 1;
     a.sl1 = wide ? (int32_t)((be1 + nt - 1) / nt) : 1;
     int64_t gx = a.nb0 * a.sl0 + (a.nbtot - a.nb0) * a.sl1;
@@ -1293,6 +1608,10 @@ hipError_t launch_reduce(const RedArgs &a0, int nsets, int lds_bytes, int block_
         launch_reduce_nt<256, RED_EPT>(a, grid, lds_bytes, s);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, int block_elems, hipStream_t s) {
+    return launch_reduce_impl(a, nsets, lds_bytes, block_elems, -1, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -33,6 +33,9 @@ struct RedArgs {
                         // central moments of every order they need)
     int32_t b;          // block size (a block of order d holds b^d entries)
     int32_t sl0, sl1;   // work-groups per block of each order (set by the launch)
+    int32_t q0, q1;     // entries per lane of each order: b^qe where the first-position
+                        // formula runs in its multi-entry form, else 1
+    int32_t gstaged;    // bit i: order d0 + i has its sub-blocks staged in LDS
     int32_t pad;
     int64_t nb0;   // blocks of the first order
     int64_t nbtot; // blocks of all orders of the launch

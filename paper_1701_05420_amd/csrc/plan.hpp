@@ -124,6 +124,10 @@ struct RedOrder {
     int64_t out_off;         // offset of this order in the per-chunk partial vector
     int32_t d, npart, nbar, b;
     int32_t nterm;           // terms of the first-position formula (orders >= 7), else 0
+    int32_t qe;              // orders >= 7: a thread of the gathering finalisation takes b^qe
+                             // consecutive entries (its last qe digits), 0: one entry
+    int32_t cstart[5];       // orders >= 7: terms grouped by the last qe positions their set A
+                             // holds; group c is terms cstart[c] .. cstart[c+1]-1
     int32_t pad2;
     int32_t ns;              // position sets of 2..d-2 positions
     int32_t lds_elems;       // doubles staged per block (0: lower orders read from memory)
