@@ -867,7 +867,7 @@ __device__ constexpr unsigned run_index(unsigned q) {
 template <int D, int NT, int EPT, int GB = 0, int GE = 0, bool GST = false>
 __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder &ro, const SetRed &sr, int64_t B,
                                                int slice, int nslice, char *dyn, int *tup, double *gred = nullptr,
-                                               const unsigned char *ptab = nullptr) {
+                                               const unsigned char *ptab = nullptr, unsigned short *ftab = nullptr) {
     constexpr int PARTS = D / 2;  // parts per partition slot
     const int tid = threadIdx.x;
     const unsigned b = (unsigned)ro.b;
@@ -1200,6 +1200,123 @@ __device__ __forceinline__ void finalize_block(const RedArgs &a, const RedOrder 
         if (sr.stamp && tid == 0) atomicMax(sr.stamp, (unsigned long long)wall_clock64());
         return;
     } else {
+        // Orders 4 to 6 by the partition recursion, sub-blocks staged, b in
+        // {2, 3, 4}: each thread takes the b entries that differ only in the
+        // last digit.  In each partition exactly one part holds the last
+        // position: its values for the b entries are one run of consecutive
+        // values of its sub-block, and each other part has one value for all
+        // of them, so a partition costs one run and one value per other
+        // part.  The in-block index of every set of the first D - 1
+        // positions comes from a per-thread LDS table (ftab), built once per
+        // entry group by one Horner step per set.
+        if constexpr (EPT > 1 && D >= 4 && D <= 6) {
+            auto rec_multi = [&](auto b_t) {
+                constexpr unsigned BB = decltype(b_t)::value, Q = BB;
+                constexpr int DP = D - 1, NS = 1 << DP;
+                constexpr int PARTS_ = D / 2;
+                unsigned short *tb = ftab + tid;  // set S at tb[S * NT]
+                const unsigned bu = be / Q;
+                for (unsigned u = (unsigned)(slice * NT + tid); u < bu; u += (unsigned)(NT * nslice)) {
+                    int rr[D];
+                    unsigned x = u;
+#pragma unroll
+                    for (int k = DP - 1; k >= 0; --k) {
+                        rr[k] = (int)(x % BB);
+                        x /= BB;
+                    }
+                    {
+                        unsigned t[NS];
+                        t[0] = 0;
+#pragma unroll
+                        for (int m = 1; m < NS; ++m) {
+                            const int k = 31 - __builtin_clz((unsigned)m);
+                            t[m] = t[m & ~(1 << k)] * BB + (unsigned)rr[k];
+                        }
+#pragma unroll
+                        for (int m = 0; m < NS; ++m) tb[m * NT] = (unsigned short)t[m];
+                    }
+                    double M[Q], sum[Q];
+#pragma unroll
+                    for (unsigned q = 0; q < Q; ++q) {
+                        rr[D - 1] = (int)q;
+                        M[q] = moment_at(rr, u * Q + q, true);
+                        sum[q] = 0.0;
+                    }
+                    const int64_t e0 = (int64_t)B * be + (int64_t)u * Q;
+                    if (sr.mom[D - 2]) {
+                        CUM_GLOBAL double *mo = gmem(sr.mom[D - 2]);
+#pragma unroll
+                        for (unsigned q = 0; q < Q; ++q) mo[e0 + q] = M[q];
+                    }
+                    // one partition's product for each entry, its parts
+                    // multiplied left to right as in the one-entry form: the
+                    // parts before the one holding the last position (pre),
+                    // that part's run, then the parts after it
+                    auto partition = [&](const int *pks, double (&prod)[Q]) {
+                        double pre = 1.0;
+                        bool held = false;
+#pragma unroll
+                        for (unsigned j = 0; j < Q; ++j) prod[j] = 0.0;
+#pragma unroll
+                        for (int pt = 0; pt < PARTS_; ++pt) {
+                            const int pk = __builtin_amdgcn_readfirstlane(pks[pt]);
+                            if (!pk) break;
+                            const unsigned mask = (unsigned)pk & 1023u;
+                            const int where = pk >> 10;
+                            const unsigned f = tb[(mask & (unsigned)(NS - 1)) * NT];
+                            if (mask >> DP & 1u) {
+#pragma unroll
+                                for (unsigned j = 0; j < Q; ++j) prod[j] = pre * sub[where + f * Q + j];
+                                held = true;
+                            } else {
+                                const double v = sub[where + f];
+                                if (held) {
+#pragma unroll
+                                    for (unsigned j = 0; j < Q; ++j) prod[j] *= v;
+                                } else {
+                                    pre *= v;
+                                }
+                            }
+                        }
+                    };
+                    int z = 0;
+                    // four partitions' factors in flight at once, added in order
+                    for (; z + 4 <= ro.npart; z += 4) {
+                        int pks[4 * PARTS_];
+#pragma unroll
+                        for (int i = 0; i < 4 * PARTS_; ++i) pks[i] = parts_g[z * PARTS_ + i];
+                        double prod[4][Q];
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) partition(pks + w * PARTS_, prod[w]);
+#pragma unroll
+                        for (int w = 0; w < 4; ++w)
+#pragma unroll
+                            for (unsigned q = 0; q < Q; ++q) sum[q] += prod[w][q];
+                    }
+                    for (; z < ro.npart; ++z) {
+                        int pks[PARTS_];
+#pragma unroll
+                        for (int i = 0; i < PARTS_; ++i) pks[i] = parts_g[z * PARTS_ + i];
+                        double prod[Q];
+                        partition(pks, prod);
+#pragma unroll
+                        for (unsigned q = 0; q < Q; ++q) sum[q] += prod[q];
+                    }
+#pragma unroll
+                    for (unsigned q = 0; q < Q; ++q) out[e0 + q] = M[q] - sum[q];
+                }
+            };
+            if (ftab && staged && b >= 2 && b <= 4) {
+                if (b == 2)
+                    rec_multi(std::integral_constant<unsigned, 2>());
+                else if (b == 3)
+                    rec_multi(std::integral_constant<unsigned, 3>());
+                else
+                    rec_multi(std::integral_constant<unsigned, 4>());
+                if (sr.stamp && tid == 0) atomicMax(sr.stamp, (unsigned long long)wall_clock64());
+                return;
+            }
+        }
         for (unsigned o0 = (unsigned)(slice * NT * EPT + tid); o0 < be; o0 += (unsigned)(NT * EPT * nslice)) {
             int r[EPT][D];  // in-block digits, first position most significant
             double M[EPT];
@@ -1419,18 +1536,25 @@ template <int D0, int NT, int EPT>
 __global__ __launch_bounds__(NT) void reduce_kernel(RedArgs a) {
     extern __shared__ __align__(16) char dyn[];
     __shared__ int tup[MAXD];
+    // launches of several entries per thread over orders 4..6: the in-block
+    // index tables of the recursion's multi-entry form, 2^(D-1) per thread
+    constexpr bool FT = EPT > 1 && D0 >= 4 && D0 <= 6;
+    constexpr int FTN = FT ? NT << (D0 + 1 >= 6 ? 5 : D0) : 1;
+    __shared__ unsigned short ftab[FTN];
     SetRed sr = a.set0;
     if (a.sets) sr = a.sets[blockIdx.y];
     const int64_t n0 = a.nb0 * a.sl0, ntot = n0 + (a.nbtot - a.nb0) * a.sl1;
     for (int64_t g = blockIdx.x; g < ntot; g += gridDim.x) {
         if (g < n0) {
             const RedOrder ro = a.ords[0];
-            finalize_block<D0, NT, EPT>(a, ro, sr, g / a.sl0, (int)(g % a.sl0), a.sl0, dyn, tup);
+            finalize_block<D0, NT, EPT>(a, ro, sr, g / a.sl0, (int)(g % a.sl0), a.sl0, dyn, tup, nullptr, nullptr,
+                                        FT ? ftab : nullptr);
         } else {
             if constexpr (D0 < MAXD) {
                 const RedOrder ro = a.ords[1];
                 const int64_t h = g - n0;
-                finalize_block<D0 + 1, NT, EPT>(a, ro, sr, h / a.sl1, (int)(h % a.sl1), a.sl1, dyn, tup);
+                finalize_block<D0 + 1, NT, EPT>(a, ro, sr, h / a.sl1, (int)(h % a.sl1), a.sl1, dyn, tup, nullptr,
+                                                nullptr, (FT && D0 + 1 <= 6) ? ftab : nullptr);
             }
         }
     }
@@ -1556,8 +1680,9 @@ static hipError_t launch_reduce_impl(const RedArgs &a0, int nsets, int lds_bytes
         a2.q0 = a.q1;
         a2.q1 = 1;
         a2.gstaged = (a.gstaged >> 1) & 1;
-        // the other order keeps the pair's one-entry-per-thread layout
-        const hipError_t e = launch_reduce_impl(a1, nsets, lds_bytes, block_elems, wide ? 1 : 0, s);
+        // the other order keeps the pair's one-entry-per-thread layout, or,
+        // at order 6 and below, takes the layout of its own order
+        const hipError_t e = launch_reduce_impl(a1, nsets, lds_bytes, block_elems, a1.d0 <= 6 ? -1 : (wide ? 1 : 0), s);
         if (e != hipSuccess) return e;
         return launch_reduce_impl(a2, nsets, lds_bytes, (int)be1, wide ? 1 : 0, s);
     }
