@@ -351,9 +351,10 @@ def bench_high_orders(torch, pc, orc, steps):
     """Orders to 8 and 10 (the recursion's partition tables grow to 715 and
     17722 terms per entry): step time, effective throughput, the split of
     kernel time between the contraction and the finalisation, and e_d of the
-    top orders against the oracle's per-entry route (FP32 requested, planner
-    defaults; from d_max = 7 on the library stages and contracts in FP64,
-    since FP32-rounded samples alone put e_8 above 1e-6)."""
+    top orders against the oracle's per-entry route (FP32 requested,
+    autotuned like the other workloads; from d_max = 7 on the library stages
+    and contracts in FP64, since FP32-rounded samples alone put e_8 above
+    1e-6)."""
     import workloads
 
     out = {}
@@ -363,7 +364,7 @@ def bench_high_orders(torch, pc, orc, steps):
         X = workloads.laplace_mix(t=t, n=n, seed=1701006)
         Xd = torch.from_numpy(X).cuda()
         flops = alg_flops(pc, t, n, d_max, b)
-        wall, kinds, o, _, pct = time_path(torch, pc, Xd, d_max, b, "f32", steps, 2, False)
+        wall, kinds, o, tuned, pct = time_path(torch, pc, Xd, d_max, b, "f32", steps, 2, True)
         ms = {k: v[0] / steps for k, v in kinds.items() if v[1]}
         Xc = X - X.mean(axis=0)
         rng = np.random.default_rng(d_max)
@@ -378,7 +379,7 @@ def bench_high_orders(torch, pc, orc, steps):
                      "ms_per_step_pct": pct, "tflops": flops / wall / 1e12,
                      "tflops_unique": uflops / wall / 1e12, "kernel_ms": ms,
                      "stored_entries": pc.plan_info(t, n, d_max, b, "f32")["stored_entries"],
-                     "rel_err_sampled": errs}
+                     "tuned": tuned, "rel_err_sampled": errs}
         log(f"  {wall * 1e3:.3f} ms/step, {flops / wall / 1e12:.2f} eff TFLOP/s; kernels {ms}; e {errs}")
     return out
 
