@@ -138,3 +138,30 @@ def test_high_order_benchmark_case(dev, orc):
         e = e_d(got, want, d)
         say(f"  e_{d} = {e:.3e}")
         assert e <= 1e-10, (d, e)
+
+
+@pytest.mark.parametrize("b", [2, 3])
+@pytest.mark.parametrize("t", [1, 2])
+def test_high_order_few_samples(dev, orc, b, t):
+    """One and two samples at orders 7 and 8, through the multi-entry
+    first-position finalisation (b = 2 reads staged sub-blocks, b = 3 reads
+    them from memory): one sample centres to zero, so every cumulant is
+    exactly 0; two samples are +-x, whose even cumulants are those of a
+    two-point law (not small against the moments) and whose odd ones vanish,
+    held to the moment scale."""
+    torch, pc = dev
+    n, dmax = 4, 8
+    say(f"high order few samples n={n} b={b} t={t} d_max={dmax}")
+    X = workloads.laplace_mix(t=t, n=n, seed=40 + t) + 2.0
+    _, K = pc.cumulants(torch.from_numpy(X).cuda(), dmax, b, "f64")
+    torch.cuda.synchronize()
+    om, OK = orc.cumulants_dense(X, dmax)
+    for d in range(2, dmax + 1):
+        got = K[d].cpu().numpy()
+        if t == 1:
+            assert not np.any(got), d
+            continue
+        want = orc.fold(OK[d], b)
+        e = e_d(got, want, d, X - om)
+        say(f"  e_{d} = {e:.3e}")
+        assert e <= 1e-10, (d, e)
