@@ -662,10 +662,13 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
 // Waves per SIMD the register allocation must allow: more resident waves
 // hide the LDS latency between the matrix instructions of any one wave.  A
 // work-group puts WG_WAVES / 4 waves on each SIMD, so the count is rounded
-// down to a multiple of that.
+// down to a multiple of that.  FP64 launches holding orders 8 or more keep
+// three: at four, their operand registers spill inside the stage loop
+// (324 bytes per lane at order 10), which took the n = 8, d <= 10
+// contraction from 0.155 to 0.254 ms.
 template <int PREC, int WN, int DMAX>
 constexpr int moment_occupancy() {
-    constexpr int want = WN == 2 ? 2 : (PREC == P_F64 ? 4 : (PREC == P_F32 ? (DMAX <= 4 ? 4 : 3) : (PREC == P_BF16X2 ? 3 : 2)));
+    constexpr int want = WN == 2 ? 2 : (PREC == P_F64 ? (DMAX <= 6 ? 4 : 3) : (PREC == P_F32 ? (DMAX <= 4 ? 4 : 3) : (PREC == P_BF16X2 ? 3 : 2)));
     constexpr int per = WG_WAVES / 4;
     return want / per * per > 0 ? want / per * per : per;
 }
