@@ -941,11 +941,30 @@ static int red_lds_layout(const RedOrder *ro, int nords, bool recursion, RedArgs
 // add up: a separate chunk-sum launch costs more than it saves there.
 constexpr int64_t SMALL_PARTIALS = (int64_t)1 << 20;
 
+// From this many sample chunks on, the contraction stores each chunk's sums
+// in tile order (whole 64-lane rows, no addresses to work out) and one pass
+// adds them over chunks and scatters them to block storage: the scatter's
+// loads and scattered stores are then paid once, not once per chunk.
+// (Calls whose contraction mixes the FP32 and FP64 accumulator layouts,
+// FP32-staged with orders of HIGH_ACC64_MIN_D and up, keep the per-chunk
+// scatter.)
+constexpr int64_t RAW_MIN_CHUNKS = 4;
+static int64_t raw_stride(const CallPlan *c) { return c->ntiles * WG_WAVES * (c->shape == TS_1x2 ? 2 : 1) * 1024; }
+static bool raw_mode(const Call &k) {
+    return k.nchunks >= RAW_MIN_CHUNKS && (k.c->prec == P_F64 || k.c->dhi < HIGH_ACC64_MIN_D);
+}
+// Bytes of the partial-sum region of a call: per-chunk block storage, or the
+// tile-order chunks followed by one block-storage copy of their sum.
+static size_t partial_bytes(const Call &k) {
+    if (raw_mode(k)) return ((size_t)k.nchunks * raw_stride(k.c) + k.c->stride) * 8;
+    return (size_t)k.nchunks * (size_t)k.c->stride * 8;
+}
+
 // The contraction of orders dlo..dhi over the staged data Xc into the
 // per-chunk partial sums, then (if always_sum, or the partial sums are not
 // small) their sum over chunks into chunk 0.  *summed tells which.
 static cum_status run_contraction(const Call &k, const void *Xc, double *partial, bool always_sum, bool *summed,
-                                  hipStream_t s) {
+                                  hipStream_t s, double **sums) {
     cum_status st = upload_call(k);
     if (st) return st;
     const CallPlan *c = k.c;
@@ -964,8 +983,23 @@ static cum_status run_contraction(const Call &k, const void *Xc, double *partial
     ma.set0.stride = c->stride;
     ma.n = c->n;
     ma.pad = 0;
+    const bool raw = raw_mode(k);
+    const int64_t rs = raw ? raw_stride(c) : 0;
+    ma.raw = raw ? partial : nullptr;
+    ma.rawstride = rs;
+    *sums = partial;
     if (nitems > 0)
         HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, c->dhi, ma, (int)nitems, s); }));
+    if (raw) {
+        double *canon = partial + k.nchunks * rs;
+        HIP_TRY(timed(CUM_KIND_REDUCE, s, [&] {
+            return launch_rawsum(partial, rs, k.nchunks, (const TileDev *)c->tiles_d.p, (const OrderDev *)c->ords_d.p,
+                                 canon, c->shape == TS_1x2 ? 2 : 1, c->prec == P_F64, s);
+        }));
+        *summed = true;
+        *sums = canon;
+        return CUM_OK;
+    }
     *summed = k.nchunks == 1 || always_sum || k.nchunks * c->stride > SMALL_PARTIALS;
     if (k.nchunks > 1 && *summed) {
         SetRed sr0;
@@ -1045,8 +1079,9 @@ static cum_status run_orders(const Call &k, const void *Xc, double *partial, dou
                              hipStream_t s, double *const *moms = nullptr) {
     cum_status st;
     bool summed;
-    if ((st = run_contraction(k, Xc, partial, false, &summed, s))) return st;
-    return run_finalize(k.c, partial, summed ? 1 : k.nchunks, k.t, outs, recursion, s, moms);
+    double *sums = nullptr;
+    if ((st = run_contraction(k, Xc, partial, false, &summed, s, &sums))) return st;
+    return run_finalize(k.c, sums, summed ? 1 : k.nchunks, k.t, outs, recursion, s, moms);
 }
 
 // Bytes of the central-moment buffers the first-position formula needs
@@ -1131,12 +1166,12 @@ cum_status cum_workspace_size(int64_t t, int n, int d_max, int b, cum_prec prec,
     size_t total = staged_bytes(t, n, prec) + align_up((size_t)groups * n * 2 * 8) + align_up((size_t)n * 8);
     Call k;
     if ((st = get_call(n, b, 2, d_max, prec, t, &k))) return st;
-    size_t part = (size_t)k.nchunks * k.c->stride * 8;
+    size_t part = partial_bytes(k);
     // a single-order moment call uses its own plan; cover the largest one
     for (int d = 2; d <= d_max; ++d) {
         Call k1;
         if ((st = get_call(n, b, d, d, prec, t, &k1))) return st;
-        part = std::max(part, (size_t)k1.nchunks * k1.c->stride * 8);
+        part = std::max(part, partial_bytes(k1));
     }
     *bytes = total + align_up(part) + moment_bytes(n, b, d_max);
     return CUM_OK;
@@ -1175,7 +1210,7 @@ cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, in
     Call k;
     if ((st = get_call(n, b, d, d, prec, t, &k))) return st;
     const size_t xbytes = staged_bytes(t, n, prec);
-    const size_t need = xbytes + align_up((size_t)k.nchunks * k.c->stride * 8);
+    const size_t need = xbytes + align_up(partial_bytes(k));
     if (!ws || ws_bytes < need) return fail(CUM_ENOMEM, "moment_blocks needs %zu workspace bytes", need);
     if ((st = upload_call(k))) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -1213,7 +1248,7 @@ static cum_status cumulants_impl(const double *X, int64_t t, int n, int64_t ldx,
     const size_t xbytes = staged_bytes(t, n, prec);
     const size_t cbytes = align_up((size_t)groups * n * 2 * 8);
     const size_t mbytes = align_up((size_t)n * 8);
-    const size_t pbytes = align_up((size_t)k.nchunks * k.c->stride * 8);
+    const size_t pbytes = align_up(partial_bytes(k));
     const size_t need = xbytes + cbytes + mbytes + pbytes + moment_bytes(n, b, d_max);
     if (noalloc) {
         if (need > NOALLOC_SCRATCH_BYTES)
@@ -1565,7 +1600,7 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
                 if ((st = get_call_cfg(n, b, bi, 2, d_max, prec, sh, tg, t, &k))) return st;
                 if ((st = upload_call(k))) return st;
                 cands.push_back(k);
-                part_max = std::max(part_max, align_up((size_t)k.nchunks * k.c->stride * 8));
+                part_max = std::max(part_max, align_up(partial_bytes(k)));
             }
     int groups;
     int64_t rows_per;
@@ -2284,7 +2319,7 @@ cum_status cum_stream_update(cum_stream *p, const double *X, int64_t t, int64_t 
     int64_t rows_per;
     center_groups(t, groups, rows_per);
     const size_t xbytes = staged_bytes(t, n, p->prec), cbytes = align_up((size_t)groups * n * 2 * 8);
-    const size_t need = xbytes + cbytes + align_up((size_t)k.nchunks * k.c->stride * 8);
+    const size_t need = xbytes + cbytes + align_up(partial_bytes(k));
     if (need > p->ws_bytes) {
         // the old workspace may still be read by work queued on the stream
         HIP_TRY(hipStreamSynchronize(s));
@@ -2311,9 +2346,10 @@ cum_status cum_stream_update(cum_stream *p, const double *X, int64_t t, int64_t 
     // the batch's sums of products of x - c, added into (or taken from) the window's
     HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, shift, Xst, p->prec, true, true, s); }));
     bool summed;
-    if ((st = run_contraction(k, Xst, partial, true, &summed, s))) return st;
+    double *sums = nullptr;
+    if ((st = run_contraction(k, Xst, partial, true, &summed, s, &sums))) return st;
     HIP_TRY(timed(CUM_KIND_REDUCE, s,
-                  [&] { return launch_axpy((double *)p->sums_d.p, partial, (double)sign, p->stride, s); }));
+                  [&] { return launch_axpy((double *)p->sums_d.p, sums, (double)sign, p->stride, s); }));
     p->t += sign * t;
     p->last = k.c;
     return CUM_OK;

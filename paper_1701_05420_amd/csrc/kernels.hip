@@ -370,7 +370,8 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 
 template <int PREC, int WN, int P, int Q>
 __device__ __forceinline__ void moment_item(const Item &item, const TileDev *tile, const OrderDev &od,
-                                            const SetDev &sd, char *lds, int n, int wave) {
+                                            const SetDev &sd, char *lds, int n, int wave, double *raw,
+                                            int64_t rawstride) {
     typedef typename PT<PREC>::T T;
     constexpr int KT = PT<PREC>::KT, KTP = PT<PREC>::KTP;
     // Orders of HIGH_ACC64_MIN_D and above in the FP32-staged precisions: the
@@ -629,6 +630,23 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
         }
     }
 
+    if (raw) {
+        // this chunk's sums in tile order: wave task (item.tile, wave), then
+        // (j, g, h) sub-block, register q, lane; 64 consecutive doubles per store
+        double *rb = raw + (int64_t)item.chunk * rawstride + ((int64_t)item.tile * WG_WAVES + wave) * (WN * 1024) + lane;
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (!(vmask >> (j * 4 + h * 2 + g) & 1u)) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        rb[((j * 2 + g) * 2 + h) * 256 + q * 64] = ACC64 ? acc64[j][h][g][q] : dacc[j][h][g][q];
+                }
+        return;
+    }
     // epilogue: write this chunk's sums at their block-storage offsets
     double *dst = sd.partial + (int64_t)item.chunk * sd.stride + od.out_off;
 #pragma unroll
@@ -692,42 +710,42 @@ __global__ __launch_bounds__(64 * WG_WAVES, (moment_occupancy<PREC, WN, DMAX>())
         const TileDev *tile = a.tiles + item.tile;
         const OrderDev od = a.ords[tile->ord];
         switch (od.p * 8 + od.q) {
-            case 1 * 8 + 1: moment_item<PREC, WN, 1, 1>(item, tile, od, sd, lds, a.n, wave); break;
-            case 1 * 8 + 2: moment_item<PREC, WN, 1, 2>(item, tile, od, sd, lds, a.n, wave); break;
-            case 2 * 8 + 2: moment_item<PREC, WN, 2, 2>(item, tile, od, sd, lds, a.n, wave); break;
+            case 1 * 8 + 1: moment_item<PREC, WN, 1, 1>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride); break;
+            case 1 * 8 + 2: moment_item<PREC, WN, 1, 2>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride); break;
+            case 2 * 8 + 2: moment_item<PREC, WN, 2, 2>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride); break;
             case 2 * 8 + 3:
                 if constexpr (DMAX >= 5)
-                    moment_item<PREC, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave);
+                    moment_item<PREC, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
                 else
                     wait_dma();
                 break;
             case 3 * 8 + 3:
                 if constexpr (DMAX >= 6)
-                    moment_item<PREC, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave);
+                    moment_item<PREC, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
                 else
                     wait_dma();
                 break;
             case 3 * 8 + 4:
                 if constexpr (DMAX >= 7)
-                    moment_item<PREC, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave);
+                    moment_item<PREC, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
                 else
                     wait_dma();
                 break;
             case 4 * 8 + 4:
                 if constexpr (DMAX >= 8)
-                    moment_item<PREC, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave);
+                    moment_item<PREC, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
                 else
                     wait_dma();
                 break;
             case 4 * 8 + 5:
                 if constexpr (DMAX >= 9)
-                    moment_item<PREC, WN, 4, 5>(item, tile, od, sd, lds, a.n, wave);
+                    moment_item<PREC, WN, 4, 5>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
                 else
                     wait_dma();
                 break;
             case 5 * 8 + 5:
                 if constexpr (DMAX >= 10)
-                    moment_item<PREC, WN, 5, 5>(item, tile, od, sd, lds, a.n, wave);
+                    moment_item<PREC, WN, 5, 5>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
                 else
                     wait_dma();
                 break;
@@ -1615,6 +1633,61 @@ __global__ __launch_bounds__(256) void chunksum_kernel(const SetRed *sets, SetRe
         for (; c < nchunks; ++c) S += pp[c * stride];
         sr.partial[e] = S;
     }
+}
+
+// The chunk sums in tile order, added over chunks and scattered once to block
+// storage: the same additions in the same order as chunksum_kernel, with the
+// address of each entry (row and column records, the (v, w) rank term)
+// worked out once instead of once per chunk in the contraction's epilogue.
+template <int WN, bool ACC64>
+__global__ __launch_bounds__(256) void rawsum_kernel(const double *raw, int64_t rawstride, int64_t nchunks,
+                                                     const TileDev *tiles, const OrderDev *ords, double *canon) {
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < rawstride; p += (int64_t)gridDim.x * 256) {
+        const int64_t wb = p / (WN * 1024);
+        const int rem = (int)(p - wb * (WN * 1024));
+        const int64_t ti = wb / WG_WAVES;
+        const int wave = (int)(wb - ti * WG_WAVES);
+        const TileDev *tile = tiles + ti;
+        if (wave >= tile->ntask) continue;
+        const WaveTask wt = tile->task[wave];
+        const int k3 = rem >> 8, q = (rem >> 6) & 3, lane = rem & 63;
+        const int j = k3 >> 2, g = (k3 >> 1) & 1, h = k3 & 1;
+        if (!((unsigned)wt.mask >> (j * 4 + h * 2 + g) & 1u)) continue;
+        const OrderDev od = ords[tile->ord];
+        const int c = wt.c0 + 32 * j + 16 * g + (lane & 15);
+        if (c >= od.nc) continue;
+        const int r = wt.r0 + 16 * h + (ACC64 ? 4 * q + (lane >> 4) : 4 * (lane >> 4) + q);
+        const Feat fr = od.rows[r], fc = od.cols[c];
+        if (fr.blk > fc.blk) continue;
+        const double *pp = raw + p;
+        double S = 0.0;
+        int64_t ch = 0;
+        for (; ch + 8 <= nchunks; ch += 8) {
+            double v[8];
+#pragma unroll
+            for (int x = 0; x < 8; ++x) v[x] = pp[(ch + x) * rawstride];
+#pragma unroll
+            for (int x = 0; x < 8; ++x) S += v[x];
+        }
+        for (; ch < nchunks; ++ch) S += pp[ch * rawstride];
+        canon[od.out_off + fr.addr + fc.addr + od.H[(int64_t)fr.blk * od.nbar + fc.blk]] = S;
+    }
+}
+
+hipError_t launch_rawsum(const double *raw, int64_t rawstride, int64_t nchunks, const TileDev *tiles,
+                         const OrderDev *ords, double *canon, int wn, bool acc64, hipStream_t s) {
+    int64_t gx = (rawstride + 255) / 256;
+    if (gx > 65535) gx = 65535;
+    if (gx < 1) gx = 1;
+    if (wn == 1 && !acc64)
+        hipLaunchKernelGGL((rawsum_kernel<1, false>), dim3((unsigned)gx), dim3(256), 0, s, raw, rawstride, nchunks, tiles, ords, canon);
+    else if (wn == 1)
+        hipLaunchKernelGGL((rawsum_kernel<1, true>), dim3((unsigned)gx), dim3(256), 0, s, raw, rawstride, nchunks, tiles, ords, canon);
+    else if (!acc64)
+        hipLaunchKernelGGL((rawsum_kernel<2, false>), dim3((unsigned)gx), dim3(256), 0, s, raw, rawstride, nchunks, tiles, ords, canon);
+    else
+        hipLaunchKernelGGL((rawsum_kernel<2, true>), dim3((unsigned)gx), dim3(256), 0, s, raw, rawstride, nchunks, tiles, ords, canon);
+    return hipGetLastError();
 }
 
 hipError_t launch_chunksum(const SetRed *sets, const SetRed &set0, int nsets, int64_t entries, hipStream_t s) {

@@ -18,6 +18,8 @@ struct MomentArgs {
     SetDev set0;
     int32_t n;           // variables; staged row n holds zeros
     int32_t pad;
+    double *raw;         // or null: each chunk's sums in tile order (see launch_rawsum)
+    int64_t rawstride;   // doubles per chunk in raw
 };
 
 struct RedArgs {
@@ -82,6 +84,11 @@ hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int
 // block_elems: b^d of the launch's first order (it picks the work-group size)
 hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, int block_elems, hipStream_t s);
 hipError_t launch_chunksum(const SetRed *sets, const SetRed &set0, int nsets, int64_t entries, hipStream_t s);
+// Chunk sums kept in tile order (raw[chunk * rawstride + p], p = position of a
+// wave task's accumulator register): add them over chunks, in chunk order,
+// and write each stored entry's sum at its block-storage offset in canon.
+hipError_t launch_rawsum(const double *raw, int64_t rawstride, int64_t nchunks, const TileDev *tiles,
+                         const OrderDev *ords, double *canon, int wn, bool acc64, hipStream_t s);
 hipError_t launch_axpy(double *y, const double *x, double a, int64_t count, hipStream_t s);
 hipError_t launch_stream_sum1(double *s1, const double *bmean, const double *shift, double tb, int n, hipStream_t s);
 hipError_t launch_stream_mean(const double *s1, const double *shift, double t, int n, double *delta, double *mean,
