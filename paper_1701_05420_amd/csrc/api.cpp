@@ -1594,14 +1594,28 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     std::vector<Call> cands;
     size_t part_max = 0;
     for (int bi : inner_candidates(b))
-        for (int sh : shapes)
+        for (int sh : shapes) {
+            int64_t ntiles = 0, nch = 0, nst = 0;
             for (int tg : targets) {
                 Call k;
                 if ((st = get_call_cfg(n, b, bi, 2, d_max, prec, sh, tg, t, &k))) return st;
                 if ((st = upload_call(k))) return st;
                 cands.push_back(k);
                 part_max = std::max(part_max, align_up(partial_bytes(k)));
+                ntiles = k.c->ntiles;
+                nch = k.nchunks;
+                nst = k.nstages;
             }
+            // Many tiles: the largest target still leaves fewer than 8 chunks.
+            // Eight put one chunk on each XCD, whose stages then fit its L2.
+            if (nch < 8 && nst >= 8 * 4 && 8 * ntiles <= INT32_MAX) {
+                Call k;
+                if ((st = get_call_cfg(n, b, bi, 2, d_max, prec, sh, (int)(8 * ntiles), t, &k))) return st;
+                if ((st = upload_call(k))) return st;
+                cands.push_back(k);
+                part_max = std::max(part_max, align_up(partial_bytes(k)));
+            }
+        }
     int groups;
     int64_t rows_per;
     center_groups(t, groups, rows_per);
