@@ -85,6 +85,13 @@ typedef enum {
                     /* over at most 64 samples, then FP64                       */
     CUM_BF16X3 = 3, /* as BF16X2 with a three-term split and the 6 cross       */
                     /* products of combined weight >= 2^-16                     */
+    CUM_F16X2 = 4,  /* FP32 data, each variable first divided by a power of    */
+                    /* two that bounds it by 32; each half-product split into  */
+                    /* FP16 hi and lo * 2^11 (22 bits), the 3 cross products   */
+                    /* hh, hl, lh on FP16 matrix cores, FP32 sums over at most */
+                    /* 64 samples, then FP64, the powers of two undone exactly */
+                    /* (orders 2..6; cum_cumulants, its no-allocation variant  */
+                    /* and cum_autotune only: elsewhere CUM_EUNSUPPORTED)      */
     /* Not precisions: these give the enum the range of int32_t, so that an
      * unknown value is a valid cum_prec object that the library rejects with
      * CUM_EUNSUPPORTED (without them, reading one is undefined in C++). */

@@ -27,7 +27,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-PRECS = {"f64": 0, "f32": 1, "bf16x2": 2, "bf16x3": 3}
+PRECS = {"f64": 0, "f32": 1, "bf16x2": 2, "bf16x3": 3, "f16x2": 4}
 MAX_ORDER = 10
 
 EXPORTS = [

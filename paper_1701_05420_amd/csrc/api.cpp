@@ -758,9 +758,9 @@ static void save_tune_file() {
 }
 
 // 32 x 32 wave tasks for FP32 and FP64 (the autotuner chose them on every
-// measured workload, orders 4 to 10); 32 x 64 for the BF16 splits, whose
-// operand arithmetic the wider task shares over twice the products.
-static int default_shape(int prec) { return (prec == P_F32 || prec == P_F64) ? TS_1x1 : TS_1x2; }
+// measured workload, orders 4 to 10) and the FP16 split; 32 x 64 for the BF16
+// splits, whose operand arithmetic the wider task shares over twice the products.
+static int default_shape(int prec) { return (prec == P_F32 || prec == P_F64 || prec == P_F16X2) ? TS_1x1 : TS_1x2; }
 constexpr int DEFAULT_TARGET = 4096;
 // The contraction computes each distinct sorted variable tuple once (inner
 // block size 1) unless tuning chose otherwise.
@@ -869,6 +869,13 @@ static cum_status get_call(int n, int b, int dlo, int dhi, int prec, int64_t t, 
 
 static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
+// The FP16 split's extra workspace: each centring group's column minima and
+// maxima, and the n + 1 per-variable powers of two the staged data are
+// divided by (0 for the other precisions).
+static size_t f16_bytes(int prec, int groups, int n) {
+    return prec == CUM_F16X2 ? align_up((size_t)groups * n * 2 * 8) + align_up((size_t)(n + 1) * 8) : 0;
+}
+
 static void center_groups(int64_t t, int &groups, int64_t &rows_per) {
     int64_t g = std::min<int64_t>(1024, (t + 255) / 256);
     if (g < 1) g = 1;
@@ -889,7 +896,7 @@ static cum_status check_common(int64_t t, int n, int b) {
 }
 
 static cum_status check_prec(int prec) {
-    if (prec < CUM_F64 || prec > CUM_BF16X3) return fail(CUM_EUNSUPPORTED, "unknown precision %d", prec);
+    if (prec < CUM_F64 || prec > CUM_F16X2) return fail(CUM_EUNSUPPORTED, "unknown precision %d", prec);
     return CUM_OK;
 }
 
@@ -964,7 +971,7 @@ static size_t partial_bytes(const Call &k) {
 // per-chunk partial sums, then (if always_sum, or the partial sums are not
 // small) their sum over chunks into chunk 0.  *summed tells which.
 static cum_status run_contraction(const Call &k, const void *Xc, double *partial, bool always_sum, bool *summed,
-                                  hipStream_t s, double **sums) {
+                                  hipStream_t s, double **sums, const double *scale = nullptr) {
     cum_status st = upload_call(k);
     if (st) return st;
     const CallPlan *c = k.c;
@@ -987,6 +994,7 @@ static cum_status run_contraction(const Call &k, const void *Xc, double *partial
     const int64_t rs = raw ? raw_stride(c) : 0;
     ma.raw = raw ? partial : nullptr;
     ma.rawstride = rs;
+    ma.scale = scale;
     *sums = partial;
     if (nitems > 0)
         HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, c->dhi, ma, (int)nitems, s); }));
@@ -1076,11 +1084,11 @@ static cum_status run_finalize(CallPlan *c, double *sums, int64_t nchunks, int64
 // moment contraction + reduction for orders dlo..dhi into outs (and the
 // recursion for d >= 4 when recursion is set)
 static cum_status run_orders(const Call &k, const void *Xc, double *partial, double *const *outs, bool recursion,
-                             hipStream_t s, double *const *moms = nullptr) {
+                             hipStream_t s, double *const *moms = nullptr, const double *scale = nullptr) {
     cum_status st;
     bool summed;
     double *sums = nullptr;
-    if ((st = run_contraction(k, Xc, partial, false, &summed, s, &sums))) return st;
+    if ((st = run_contraction(k, Xc, partial, false, &summed, s, &sums, scale))) return st;
     return run_finalize(k.c, sums, summed ? 1 : k.nchunks, k.t, outs, recursion, s, moms);
 }
 
@@ -1163,7 +1171,8 @@ cum_status cum_workspace_size(int64_t t, int n, int d_max, int b, cum_prec prec,
     int groups;
     int64_t rows_per;
     center_groups(t, groups, rows_per);
-    size_t total = staged_bytes(t, n, prec) + align_up((size_t)groups * n * 2 * 8) + align_up((size_t)n * 8);
+    size_t total = staged_bytes(t, n, prec) + align_up((size_t)groups * n * 2 * 8) + align_up((size_t)n * 8) +
+                   f16_bytes(prec, groups, n);
     Call k;
     if ((st = get_call(n, b, 2, d_max, prec, t, &k))) return st;
     size_t part = partial_bytes(k);
@@ -1174,6 +1183,34 @@ cum_status cum_workspace_size(int64_t t, int n, int d_max, int b, cum_prec prec,
         part = std::max(part, partial_bytes(k1));
     }
     *bytes = total + align_up(part) + moment_bytes(n, b, d_max);
+    return CUM_OK;
+}
+
+static cum_status center_impl(const double *X, int64_t t, int n, int64_t ldx, int prec, double *mean, void *Xc,
+                              char *ws, size_t ws_bytes, hipStream_t s);
+
+// Centring and staging of a call that centres its own data: column sums and
+// means, then the staged layout (FP16 split: also the per-variable scales,
+// written to f16w + the minima / maxima part; returned in *scale).
+static cum_status center_and_stage(const double *X, int64_t t, int n, int64_t ldx, int prec, double *mu, char *cw,
+                                   size_t cbytes, char *Xst, char *f16w, const double **scale, hipStream_t s) {
+    *scale = nullptr;
+    int groups;
+    int64_t rows_per;
+    center_groups(t, groups, rows_per);
+    if (prec == CUM_F16X2) {
+        if (cbytes < align_up((size_t)groups * n * 2 * 8) || !f16w) return fail(CUM_ENOMEM, "centring workspace");
+        double *part = (double *)cw, *mm = (double *)f16w;
+        double *sc = (double *)(f16w + align_up((size_t)groups * n * 2 * 8));
+        HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_colsum(X, t, n, ldx, rows_per, groups, part, s, mm); }));
+        HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_mean(part, groups, n, t, mu, s, mm, sc); }));
+        HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, mu, Xst, prec, true, true, s, sc); }));
+        *scale = sc;
+        return CUM_OK;
+    }
+    cum_status st = center_impl(X, t, n, ldx, prec, mu, nullptr, cw, cbytes, s);
+    if (st) return st;
+    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, mu, Xst, prec, true, true, s); }));
     return CUM_OK;
 }
 
@@ -1204,6 +1241,8 @@ cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, in
                              size_t ws_bytes, void *stream) {
     cum_status st;
     if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;
+    if (prec == CUM_F16X2)
+        return fail(CUM_EUNSUPPORTED, "the FP16 split scales the data it centres itself: use cum_cumulants");
     if (d < 2 || d > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d must be in 2..%d", CUM_MAX_ORDER);
     if (!Xc || !M) return fail(CUM_EINVAL, "Xc and M must not be NULL");
     std::lock_guard<std::mutex> lk(g_mu);
@@ -1249,7 +1288,8 @@ static cum_status cumulants_impl(const double *X, int64_t t, int n, int64_t ldx,
     const size_t cbytes = align_up((size_t)groups * n * 2 * 8);
     const size_t mbytes = align_up((size_t)n * 8);
     const size_t pbytes = align_up(partial_bytes(k));
-    const size_t need = xbytes + cbytes + mbytes + pbytes + moment_bytes(n, b, d_max);
+    const size_t lbytes = moment_bytes(n, b, d_max);
+    const size_t need = xbytes + cbytes + mbytes + pbytes + lbytes + f16_bytes(prec, groups, n);
     if (noalloc) {
         if (need > NOALLOC_SCRATCH_BYTES)
             return fail(CUM_ENOMEM, "this call needs %zu bytes of scratch; the fixed scratch holds %zu", need,
@@ -1276,8 +1316,10 @@ static cum_status cumulants_impl(const double *X, int64_t t, int n, int64_t ldx,
     hipStream_t s = (hipStream_t)stream;
     double *mu = mean ? mean : mtmp;
     if ((st = upload_call(k))) return st;
-    if ((st = center_impl(X, t, n, ldx, prec, mu, nullptr, cw, cbytes, s))) return st;
-    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, mu, Xst, prec, true, true, s); }));
+    const double *scale = nullptr;
+    if ((st = center_and_stage(X, t, n, ldx, prec, mu, cw, cbytes, Xst, w + xbytes + cbytes + mbytes + pbytes + lbytes,
+                               &scale, s)))
+        return st;
     // central moments of the lower orders for the first-position formula
     double *moms[MAXD - 1] = {nullptr};
     double *const *mp = nullptr;
@@ -1290,7 +1332,7 @@ static cum_status cumulants_impl(const double *X, int64_t t, int n, int64_t ldx,
         }
         mp = moms;
     }
-    return run_orders(k, Xst, partial, kappa, true, s, mp);
+    return run_orders(k, Xst, partial, kappa, true, s, mp, scale);
 }
 
 cum_status cum_cumulants(const double *X, int64_t t, int n, int64_t ldx, int d_max, int b, cum_prec prec,
@@ -1625,7 +1667,8 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
     // finalisation cum_cumulants runs (the first-position form)
     const size_t lbytes = moment_bytes(n, b, d_max);
     DevBuf ws;
-    HIP_TRY(hipMalloc(&ws.p, xbytes + cbytes + mbytes + kbytes + part_max + lbytes));
+    const size_t fbytes = f16_bytes(prec, groups, n);
+    HIP_TRY(hipMalloc(&ws.p, xbytes + cbytes + mbytes + kbytes + part_max + lbytes + fbytes));
     char *w = (char *)ws.p;
     char *Xst = w, *cw = w + xbytes;
     double *mu = (double *)(w + xbytes + cbytes), *kap = (double *)(w + xbytes + cbytes + mbytes);
@@ -1643,8 +1686,10 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
         }
         mp = moms;
     }
-    if ((st = center_impl(X, t, n, ldx, prec, mu, nullptr, cw, cbytes, s))) return st;
-    HIP_TRY(launch_stage(X, t, n, ldx, mu, Xst, prec, true, true, s));
+    const double *scale = nullptr;
+    if ((st = center_and_stage(X, t, n, ldx, prec, mu, cw, cbytes, Xst,
+                               w + xbytes + cbytes + mbytes + kbytes + part_max + lbytes, &scale, s)))
+        return st;
     // timing of the library's own launches is off while candidates run; the
     // events and that switch are restored on every way out
     struct Guard {
@@ -1665,7 +1710,7 @@ cum_status cum_autotune(const double *X, int64_t t, int n, int64_t ldx, int d_ma
         float cand_ms = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
             HIP_TRY(hipEventRecord(gd.e0, s));
-            if ((st = run_orders(c, Xst, partial, outs, true, s, mp))) return st;
+            if ((st = run_orders(c, Xst, partial, outs, true, s, mp, scale))) return st;
             HIP_TRY(hipEventRecord(gd.e1, s));
             HIP_TRY(hipEventSynchronize(gd.e1));
             float ms = 0.f;
@@ -1995,6 +2040,7 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
     *plan = nullptr;
     if (n_sets < 1 || n_sets > 65535) return fail(CUM_EINVAL, "n_sets must be in 1..65535");
     if ((st = check_common(1, n, b)) || (st = check_prec(prec))) return st;
+    if (prec == CUM_F16X2) return fail(CUM_EUNSUPPORTED, "batches and streams do not take the FP16 split");
     if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
     prec = (cum_prec)staged_prec(prec, d_max);
     for (int s = 0; s < n_sets; ++s)
@@ -2267,6 +2313,7 @@ cum_status cum_stream_create(int n, int d_max, int b, cum_prec prec, const doubl
     if (!out) return fail(CUM_EINVAL, "NULL argument");
     *out = nullptr;
     if ((st = check_common(1, n, b)) || (st = check_prec(prec))) return st;
+    if (prec == CUM_F16X2) return fail(CUM_EUNSUPPORTED, "batches and streams do not take the FP16 split");
     if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
     prec = (cum_prec)staged_prec(prec, d_max);
     for (int d = 2; d <= d_max; ++d)

@@ -58,13 +58,16 @@ __device__ __forceinline__ int64_t ipow_dev(int b, int e) {
 // centring (Def. of the centred variable): FP64 column sums in a fixed order,
 // Neumaier-compensated; then x - mean in FP64, stored in the device precision.
 // ---------------------------------------------------------------------------
+// MM: also each column's minimum and maximum over the group (mm)
+template <bool MM = false>
 __device__ __forceinline__ void colsum_body(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int g,
-                                            double *part) {
+                                            double *part, double *mm = nullptr) {
     __shared__ double ss[256], cs[256];
+    __shared__ double lo_s[MM ? 256 : 1], hi_s[MM ? 256 : 1];
     const int tid = threadIdx.x;
     const int R = 256 / n;
     const int col = tid % n, rl = tid / n;
-    double s = 0.0, c = 0.0;
+    double s = 0.0, c = 0.0, lo = INFINITY, hi = -INFINITY;
     const int64_t r0 = (int64_t)g * rows_per;
     const int64_t r1 = min(t, r0 + rows_per);
     if (rl < R) {
@@ -75,41 +78,83 @@ __device__ __forceinline__ void colsum_body(const double *X, int64_t t, int n, i
 #pragma unroll
             for (int u = 0; u < 8; ++u) x[u] = X[(r + u * R) * ldx + col];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) neumaier(s, c, x[u]);
+            for (int u = 0; u < 8; ++u) {
+                neumaier(s, c, x[u]);
+                if constexpr (MM) {
+                    lo = fmin(lo, x[u]);
+                    hi = fmax(hi, x[u]);
+                }
+            }
         }
-        for (; r < r1; r += R) neumaier(s, c, X[r * ldx + col]);
+        for (; r < r1; r += R) {
+            const double x = X[r * ldx + col];
+            neumaier(s, c, x);
+            if constexpr (MM) {
+                lo = fmin(lo, x);
+                hi = fmax(hi, x);
+            }
+        }
     }
     ss[tid] = s;
     cs[tid] = c;
+    if constexpr (MM) {
+        lo_s[tid] = lo;
+        hi_s[tid] = hi;
+    }
     __syncthreads();
     if (tid < n) {
-        double S = 0.0, C = 0.0;
+        double S = 0.0, C = 0.0, L = INFINITY, H = -INFINITY;
         for (int k = 0; k < R; ++k) {
             neumaier(S, C, ss[k * n + tid]);
             neumaier(S, C, cs[k * n + tid]);
+            if constexpr (MM) {
+                L = fmin(L, lo_s[k * n + tid]);
+                H = fmax(H, hi_s[k * n + tid]);
+            }
         }
         part[((int64_t)g * n + tid) * 2] = S;
         part[((int64_t)g * n + tid) * 2 + 1] = C;
+        if constexpr (MM) {
+            mm[((int64_t)g * n + tid) * 2] = L;
+            mm[((int64_t)g * n + tid) * 2 + 1] = H;
+        }
     }
 }
 
+template <bool MM>
 __global__ __launch_bounds__(256) void colsum_kernel(const double *X, int64_t t, int n, int64_t ldx,
-                                                     int64_t rows_per, double *part) {
-    colsum_body(X, t, n, ldx, rows_per, blockIdx.x, part);
+                                                     int64_t rows_per, double *part, double *mm) {
+    colsum_body<MM>(X, t, n, ldx, rows_per, blockIdx.x, part, mm);
 }
 
 // One work-group per column: thread k sums groups k, k+256, ...; the 256
 // compensated partials are then combined pairwise in a fixed tree.
-__device__ __forceinline__ void mean_body(const double *part, int groups, int n, int64_t t, double *mean, int i) {
+// MM (the FP16 split): from the groups' minima and maxima, also the power of
+// two scale[i] = 2^(e - 5), where a = max |x - mean| over the column lies in
+// [2^(e-1), 2^e) (scale 1 for a constant column), and scale[n] = 1.  Divided
+// by it, every centred value is below 32 in magnitude, so a product of up to
+// three of them stays below the FP16 maximum (65504).
+template <bool MM = false>
+__device__ __forceinline__ void mean_body(const double *part, int groups, int n, int64_t t, double *mean, int i,
+                                          const double *mm = nullptr, double *scale = nullptr) {
     __shared__ double ss[256], cs[256];
+    __shared__ double lo_s[MM ? 256 : 1], hi_s[MM ? 256 : 1];
     const int tid = threadIdx.x;
-    double S = 0.0, C = 0.0;
+    double S = 0.0, C = 0.0, L = INFINITY, H = -INFINITY;
     for (int g = tid; g < groups; g += 256) {
         neumaier(S, C, part[((int64_t)g * n + i) * 2]);
         neumaier(S, C, part[((int64_t)g * n + i) * 2 + 1]);
+        if constexpr (MM) {
+            L = fmin(L, mm[((int64_t)g * n + i) * 2]);
+            H = fmax(H, mm[((int64_t)g * n + i) * 2 + 1]);
+        }
     }
     ss[tid] = S;
     cs[tid] = C;
+    if constexpr (MM) {
+        lo_s[tid] = L;
+        hi_s[tid] = H;
+    }
     for (int w = 128; w > 0; w >>= 1) {
         __syncthreads();
         if (tid < w) {
@@ -118,14 +163,31 @@ __device__ __forceinline__ void mean_body(const double *part, int groups, int n,
             neumaier(S2, C2, cs[tid + w]);
             ss[tid] = S2;
             cs[tid] = C2;
+            if constexpr (MM) {
+                lo_s[tid] = fmin(lo_s[tid], lo_s[tid + w]);
+                hi_s[tid] = fmax(hi_s[tid], hi_s[tid + w]);
+            }
         }
     }
-    if (tid == 0) mean[i] = (ss[0] + cs[0]) / (double)t;
+    if (tid == 0) {
+        const double mu = (ss[0] + cs[0]) / (double)t;
+        mean[i] = mu;
+        if constexpr (MM) {
+            const double a = fmax(hi_s[0] - mu, mu - lo_s[0]);
+            int e = 0;
+            if (a > 0.0) {
+                (void)frexp(a, &e);  // a = f * 2^e, f in [0.5, 1): 2^e >= a
+            }
+            scale[i] = a > 0.0 ? ldexp(1.0, e - 5) : 1.0;
+            if (i == 0) scale[n] = 1.0;
+        }
+    }
 }
 
+template <bool MM>
 __global__ __launch_bounds__(256) void mean_kernel(const double *part, int groups, int n, int64_t t,
-                                                   double *mean) {
-    mean_body(part, groups, n, t, mean, blockIdx.x);
+                                                   double *mean, const double *mm, double *scale) {
+    mean_body<MM>(part, groups, n, t, mean, blockIdx.x, mm, scale);
 }
 
 template <typename T>
@@ -159,9 +221,9 @@ __global__ void stamp_kernel(unsigned long long *where) {
 // One work-group per stage; variables are moved through LDS in groups of 32
 // so that both the row-major reads and the stage writes are contiguous.
 // ---------------------------------------------------------------------------
-template <typename TI, typename TO, bool CENTER>
+template <typename TI, typename TO, bool CENTER, bool SCALED = false>
 __device__ __forceinline__ void stage_body(const TI *X, int64_t t, int n, int64_t ldx, const double *mean, TO *Xst,
-                                           int KT, int KTP, int64_t s) {
+                                           int KT, int KTP, int64_t s, const double *scale = nullptr) {
     __shared__ double tile[64][33];
     const int tid = threadIdx.x;
     const int64_t l0 = s * KT;
@@ -174,6 +236,7 @@ __device__ __forceinline__ void stage_body(const TI *X, int64_t t, int n, int64_
             if (v < n && l0 + k < t) {
                 x = (double)X[(l0 + k) * ldx + v];
                 if (CENTER) x -= mean[v];
+                if constexpr (SCALED) x /= scale[v];  // a power of two: exact
             }
             tile[k][e & 31] = x;
         }
@@ -192,11 +255,25 @@ __global__ __launch_bounds__(256) void stage_kernel(const TI *X, int64_t t, int 
     for (int64_t s = blockIdx.x; s < nstages; s += gridDim.x) stage_body<TI, TO, CENTER>(X, t, n, ldx, mean, Xst, KT, KTP, s);
 }
 
+// centred FP64 data divided by per-variable powers of two, to FP32 (FP16 split)
+__global__ __launch_bounds__(256) void stage_scaled_kernel(const double *X, int64_t t, int n, int64_t ldx,
+                                                           const double *mean, const double *scale, float *Xst,
+                                                           int KT, int KTP, int64_t nstages) {
+    for (int64_t s = blockIdx.x; s < nstages; s += gridDim.x)
+        stage_body<double, float, true, true>(X, t, n, ldx, mean, Xst, KT, KTP, s, scale);
+}
+
 hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xst, int prec,
-                        bool center, bool in_f64, hipStream_t s) {
+                        bool center, bool in_f64, hipStream_t s, const double *scale) {
     const int KT = stage_kt(prec), KTP = stage_pitch(prec);
     const int64_t nst = (t + KT - 1) / KT;
     const unsigned grid = (unsigned)std::min<int64_t>(nst, 65535);
+    if (scale) {
+        if (!center || !in_f64 || prec == P_F64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(stage_scaled_kernel, dim3(grid), dim3(256), 0, s, (const double *)X, t, n, ldx, mean, scale,
+                           (float *)Xst, KT, KTP, nst);
+        return hipGetLastError();
+    }
     if (center) {
         if (prec == P_F64)
             hipLaunchKernelGGL((stage_kernel<double, double, true>), dim3(grid), dim3(256), 0, s, (const double *)X, t,
@@ -288,11 +365,17 @@ struct PT<P_BF16X3> {
     typedef float T;
     enum { KT = 64, KTP = 68 };
 };
+template <>
+struct PT<P_F16X2> {
+    typedef float T;
+    enum { KT = 64, KTP = 68 };
+};
 
 int lds_bytes_moment(int prec, int n) { return 2 * (n + 1) * stage_pitch(prec) * stage_esize(prec); }
 static_assert(PT<P_F64>::KTP == stage_pitch(P_F64) && PT<P_F32>::KTP == stage_pitch(P_F32) &&
                   PT<P_BF16X2>::KTP == stage_pitch(P_BF16X2) && PT<P_F64>::KT == stage_kt(P_F64) &&
-                  PT<P_F32>::KT == stage_kt(P_F32) && PT<P_BF16X2>::KT == stage_kt(P_BF16X2),
+                  PT<P_F32>::KT == stage_kt(P_F32) && PT<P_BF16X2>::KT == stage_kt(P_BF16X2) &&
+                  PT<P_F16X2>::KTP == stage_pitch(P_F16X2) && PT<P_F16X2>::KT == stage_kt(P_F16X2),
               "stage constants");
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -320,6 +403,26 @@ __device__ __forceinline__ f2 to_f2(bf2 x) { return __builtin_convertvector(x, f
 
 // Two terms: hi, and lo = x - hi rounded (the compiler may form x - hi from
 // the unrounded product with one fused multiply-add, which only helps lo).
+// FP16 split of eight FP32 values: hi = fp16(v) (nearest even) and
+// lo = fp16((v - hi) * 2^11).  v - hi is exact in FP32 and 2^11 times it is
+// of the order of v, so lo keeps FP16's full 11 bits where (v - hi) itself
+// would fall into FP16's subnormal range; hi + lo / 2^11 carries 22 bits of v.
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_f16(const float *v, h8 &hi, h8 &lo) {
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+        const f2 x = {v[k], v[k + 1]};
+        const h2 h = __builtin_convertvector(x, h2);
+        const f2 r = (x - __builtin_convertvector(h, f2)) * 2048.f;
+        const h2 l = __builtin_convertvector(r, h2);
+        hi[k] = h[0];
+        hi[k + 1] = h[1];
+        lo[k] = l[0];
+        lo[k + 1] = l[1];
+    }
+}
+
 __device__ __forceinline__ void split2(const float *v, bf8 &hi, bf8 &lo) {
 #pragma unroll
     for (int k = 0; k < 8; k += 2) {
@@ -371,7 +474,7 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 template <int PREC, int WN, int P, int Q>
 __device__ __forceinline__ void moment_item(const Item &item, const TileDev *tile, const OrderDev &od,
                                             const SetDev &sd, char *lds, int n, int wave, double *raw,
-                                            int64_t rawstride) {
+                                            int64_t rawstride, const double *scale) {
     typedef typename PT<PREC>::T T;
     constexpr int KT = PT<PREC>::KT, KTP = PT<PREC>::KTP;
     // Orders of HIGH_ACC64_MIN_D and above in the FP32-staged precisions: the
@@ -384,7 +487,8 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
     constexpr bool HI = PREC != P_F64 && P + Q >= HIGH_ACC64_MIN_D;
     constexpr bool ACC64 = PREC == P_F64 || HI;  // FP64 accumulators (FP64 16x16 output layout)
     constexpr bool BF = PREC >= P_BF16X2 && !HI;
-    constexpr int NS = (PREC == P_BF16X3) ? 3 : 2;  // split terms (BF16 paths)
+    constexpr bool F16 = PREC == P_F16X2 && !HI;     // FP16 hi and scaled lo (split_f16)
+    constexpr int NS = (PREC == P_BF16X3) ? 3 : 2;  // split terms (BF16 and FP16 paths)
     // samples per step group: lane group g (= lane / 16) holds VEC consecutive samples
     constexpr int VEC = (PREC == P_F64) ? 2 : (PREC == P_F32 || HI ? 4 : 8);
     constexpr int STEP = 4 * VEC;
@@ -515,6 +619,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                             }
                 } else {
                     bf8 As[2][NS], Bs[WN][2][NS];
+                    h8 Ah[2][2], Bh[WN][2][2];  // FP16 split: hi, 2^11-scaled lo
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         f4 v0 = *reinterpret_cast<const f4 *>(xb + roff[h][0] + kk);
@@ -525,7 +630,9 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                             v1 *= *reinterpret_cast<const f4 *>(xb + roff[h][q] + kk + 4);
                         }
                         float v[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
-                        if constexpr (NS == 3)
+                        if constexpr (F16)
+                            split_f16(v, Ah[h][0], Ah[h][1]);
+                        else if constexpr (NS == 3)
                             split3(v, As[h][0], As[h][1], As[h][2]);
                         else
                             split2(v, As[h][0], As[h][1]);
@@ -542,11 +649,34 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                                 v1 *= *reinterpret_cast<const f4 *>(xb + coff[j][g][q] + kk + 4);
                             }
                             float v[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
-                            if constexpr (NS == 3)
+                            if constexpr (F16)
+                                split_f16(v, Bh[j][g][0], Bh[j][g][1]);
+                            else if constexpr (NS == 3)
                                 split3(v, Bs[j][g][0], Bs[j][g][1], Bs[j][g][2]);
                             else
                                 split2(v, Bs[j][g][0], Bs[j][g][1]);
                         }
+                    // FP16 split: hh in acc; hl and lh (each 2^11 times its weight) in
+                    // acc2; ll (weight 2^-22) is left out
+                    if constexpr (F16) {
+#pragma unroll
+                        for (int pr = 2; pr >= 0; --pr)
+#pragma unroll
+                            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                                    for (int g = 0; g < 2; ++g)
+                                        if (all || (vmask >> (j * 4 + h * 2 + g) & 1u)) {
+                                            if (pr == 0)
+                                                acc[j][h][g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                                    Ah[h][0], Bh[j][g][0], acc[j][h][g], 0, 0, 0);
+                                            else
+                                                acc2[j][h][g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                                    Ah[h][pr == 1 ? 0 : 1], Bh[j][g][pr == 1 ? 1 : 0],
+                                                    acc2[j][h][g], 0, 0, 0);
+                                        }
+                    } else {
                     // cross products of the split terms: all 4 for two terms; for three
                     // terms the 6 of combined weight >= 2^-16 (hh, hm, mh, hl, lh, mm),
                     // hh in its own accumulator so that the five small products do not
@@ -574,6 +704,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                                             acc[j][h][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                                                 As[h][ia], Bs[j][g][ib], acc[j][h][g], 0, 0, 0);
                                     }
+                    }
                 }
             }
                 };
@@ -614,7 +745,9 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                                 acc[j][h][g][q] = 0.f;
                             }
             }
-            if (PREC == P_BF16X3 && fourth) {
+            if ((PREC == P_BF16X3 || PREC == P_F16X2) && fourth) {
+                // the FP16 split's hl + lh sums carry the factor 2^11 of its lo terms
+                constexpr double w2 = PREC == P_F16X2 ? 0x1p-11 : 1.0;
 #pragma unroll
                 for (int j = 0; j < WN; ++j)
 #pragma unroll
@@ -623,13 +756,49 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
                         for (int g = 0; g < 2; ++g)
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
-                                dacc[j][h][g][q] += (double)acc2[j][h][g][q];
+                                dacc[j][h][g][q] += (double)acc2[j][h][g][q] * w2;
                                 acc2[j][h][g][q] = 0.f;
                             }
             }
         }
     }
 
+    if constexpr (F16) {
+        // undo the staging's per-variable powers of two (exact): each sum of
+        // products of row and column operands times the scales of their variables
+        double cs[WN][2], rs[2][4];
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const int c = cbase + 32 * j + 16 * g + (lane & 15);
+                double v = 1.0;
+                if (c < od.nc) {
+                    const Feat fc = od.cols[c];
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) v *= scale[fc.var[q]];
+                }
+                cs[j][g] = v;
+            }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const Feat fr = od.rows[rbase + 16 * h + 4 * (lane >> 4) + q];
+                double v = 1.0;
+#pragma unroll
+                for (int p = 0; p < P; ++p) v *= scale[fr.var[p]];
+                rs[h][q] = v;
+            }
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int g = 0; g < 2; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dacc[j][h][g][q] *= rs[h][q] * cs[j][g];
+    }
     if (raw) {
         // this chunk's sums in tile order: wave task (item.tile, wave), then
         // (j, g, h) sub-block, register q, lane; 64 consecutive doubles per store
@@ -686,7 +855,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
 // contraction from 0.155 to 0.254 ms.
 template <int PREC, int WN, int DMAX>
 constexpr int moment_occupancy() {
-    constexpr int want = WN == 2 ? 2 : (PREC == P_F64 ? (DMAX <= 6 ? 4 : 3) : (PREC == P_F32 ? (DMAX <= 4 ? 4 : 3) : (PREC == P_BF16X2 ? 3 : 2)));
+    constexpr int want = WN == 2 ? 2 : (PREC == P_F64 ? (DMAX <= 6 ? 4 : 3) : (PREC == P_F32 ? (DMAX <= 4 ? 4 : 3) : (PREC == P_BF16X2 || PREC == P_F16X2 ? 3 : 2)));
     constexpr int per = WG_WAVES / 4;
     return want / per * per > 0 ? want / per * per : per;
 }
@@ -710,42 +879,42 @@ __global__ __launch_bounds__(64 * WG_WAVES, (moment_occupancy<PREC, WN, DMAX>())
         const TileDev *tile = a.tiles + item.tile;
         const OrderDev od = a.ords[tile->ord];
         switch (od.p * 8 + od.q) {
-            case 1 * 8 + 1: moment_item<PREC, WN, 1, 1>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride); break;
-            case 1 * 8 + 2: moment_item<PREC, WN, 1, 2>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride); break;
-            case 2 * 8 + 2: moment_item<PREC, WN, 2, 2>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride); break;
+            case 1 * 8 + 1: moment_item<PREC, WN, 1, 1>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride, a.scale); break;
+            case 1 * 8 + 2: moment_item<PREC, WN, 1, 2>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride, a.scale); break;
+            case 2 * 8 + 2: moment_item<PREC, WN, 2, 2>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride, a.scale); break;
             case 2 * 8 + 3:
                 if constexpr (DMAX >= 5)
-                    moment_item<PREC, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
+                    moment_item<PREC, WN, 2, 3>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride, a.scale);
                 else
                     wait_dma();
                 break;
             case 3 * 8 + 3:
                 if constexpr (DMAX >= 6)
-                    moment_item<PREC, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
+                    moment_item<PREC, WN, 3, 3>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride, a.scale);
                 else
                     wait_dma();
                 break;
             case 3 * 8 + 4:
                 if constexpr (DMAX >= 7)
-                    moment_item<PREC, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
+                    moment_item<PREC, WN, 3, 4>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride, a.scale);
                 else
                     wait_dma();
                 break;
             case 4 * 8 + 4:
                 if constexpr (DMAX >= 8)
-                    moment_item<PREC, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
+                    moment_item<PREC, WN, 4, 4>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride, a.scale);
                 else
                     wait_dma();
                 break;
             case 4 * 8 + 5:
                 if constexpr (DMAX >= 9)
-                    moment_item<PREC, WN, 4, 5>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
+                    moment_item<PREC, WN, 4, 5>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride, a.scale);
                 else
                     wait_dma();
                 break;
             case 5 * 8 + 5:
                 if constexpr (DMAX >= 10)
-                    moment_item<PREC, WN, 5, 5>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride);
+                    moment_item<PREC, WN, 5, 5>(item, tile, od, sd, lds, a.n, wave, a.raw, a.rawstride, a.scale);
                 else
                     wait_dma();
                 break;
@@ -764,6 +933,8 @@ static void launch_moment_dmax(int dmax, const MomentArgs &a, int grid, int lds,
         hipLaunchKernelGGL((moment_kernel<PREC, WN, 4>), dim3(grid), dim3(64 * WG_WAVES), lds, s, a);
     else if (dmax <= 6)
         hipLaunchKernelGGL((moment_kernel<PREC, WN, 6>), dim3(grid), dim3(64 * WG_WAVES), lds, s, a);
+    else if constexpr (PREC == P_F16X2)
+        return;  // orders >= 7 stage in FP64 (the host refuses the FP16 split there)
     else if (dmax <= 8)
         hipLaunchKernelGGL((moment_kernel<PREC, WN, 8>), dim3(grid), dim3(64 * WG_WAVES), lds, s, a);
     else
@@ -786,6 +957,9 @@ hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int
         case P_F64: return launch_moment_prec<P_F64>(shape, dmax, a, grid, s);
         case P_F32: return launch_moment_prec<P_F32>(shape, dmax, a, grid, s);
         case P_BF16X2: return launch_moment_prec<P_BF16X2>(shape, dmax, a, grid, s);
+        case P_F16X2:
+            if (dmax > 6 || !a.scale) return hipErrorInvalidValue;
+            return launch_moment_prec<P_F16X2>(shape, dmax, a, grid, s);
         default: return launch_moment_prec<P_BF16X3>(shape, dmax, a, grid, s);
     }
 }
@@ -2045,13 +2219,20 @@ hipError_t launch_unfold(const double *blocks, int n, int d, int b, double *dens
 // centring launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(colsum_kernel, dim3(groups), dim3(256), 0, s, X, t, n, ldx, rows_per, part);
+                         hipStream_t s, double *mm) {
+    if (mm)
+        hipLaunchKernelGGL(colsum_kernel<true>, dim3(groups), dim3(256), 0, s, X, t, n, ldx, rows_per, part, mm);
+    else
+        hipLaunchKernelGGL(colsum_kernel<false>, dim3(groups), dim3(256), 0, s, X, t, n, ldx, rows_per, part, mm);
     return hipGetLastError();
 }
 
-hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s) {
-    hipLaunchKernelGGL(mean_kernel, dim3(n), dim3(256), 0, s, part, groups, n, t, mean);
+hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s,
+                       const double *mm, double *scale) {
+    if (mm && scale)
+        hipLaunchKernelGGL(mean_kernel<true>, dim3(n), dim3(256), 0, s, part, groups, n, t, mean, mm, scale);
+    else
+        hipLaunchKernelGGL(mean_kernel<false>, dim3(n), dim3(256), 0, s, part, groups, n, t, mean, nullptr, nullptr);
     return hipGetLastError();
 }
 

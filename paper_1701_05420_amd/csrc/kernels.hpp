@@ -7,7 +7,7 @@
 
 namespace cum {
 
-enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X2 = 2, P_BF16X3 = 3 };
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X2 = 2, P_BF16X3 = 3, P_F16X2 = 4 };
 
 struct MomentArgs {
     const OrderDev *ords;
@@ -20,6 +20,8 @@ struct MomentArgs {
     int32_t pad;
     double *raw;         // or null: each chunk's sums in tile order (see launch_rawsum)
     int64_t rawstride;   // doubles per chunk in raw
+    const double *scale; // FP16 split: the power of two each staged row was divided by
+                         // (n + 1 entries, the zero row's 1), else null
 };
 
 struct RedArgs {
@@ -77,9 +79,10 @@ struct MoebArgs {
 enum TileShape { TS_1x1 = 0, TS_1x2 = 2 };
 
 int lds_bytes_moment(int prec, int n);
-// row-major data (FP64 with ldx, or FP32 with ldx) -> staged layout, optionally centred
+// row-major data (FP64 with ldx, or FP32 with ldx) -> staged layout, optionally centred;
+// with scale (FP16 split, centred FP64 input only), variable v is divided by scale[v]
 hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xst, int prec,
-                        bool center, bool in_f64, hipStream_t s);
+                        bool center, bool in_f64, hipStream_t s, const double *scale = nullptr);
 hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s);
 // block_elems: b^d of the launch's first order (it picks the work-group size)
 hipError_t launch_reduce(const RedArgs &a, int nsets, int lds_bytes, int block_elems, hipStream_t s);
@@ -95,9 +98,13 @@ hipError_t launch_stream_mean(const double *s1, const double *shift, double t, i
                               hipStream_t s);
 hipError_t launch_recentre(const RecArgs &a, hipStream_t s);
 hipError_t launch_moebius(const MoebArgs &a, hipStream_t s);
+// With mm (groups x n x 2 doubles), the column sums also record each
+// group's column minima and maxima; launch_mean then also writes scale
+// (n + 1 doubles) for the FP16 split: see launch_mean.
 hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,
-                         hipStream_t s);
-hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s);
+                         hipStream_t s, double *mm = nullptr);
+hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s,
+                       const double *mm = nullptr, double *scale = nullptr);
 hipError_t launch_center(const double *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xc, int prec,
                          hipStream_t s);
 hipError_t launch_unfold(const double *blocks, int n, int d, int b, double *dense, hipStream_t s);

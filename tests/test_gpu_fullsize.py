@@ -11,7 +11,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
+TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6, "f16x2": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -73,9 +73,9 @@ def sampled_check(pc, orc, Xc, K, n, dmax, b, precs, count, seed):
 
 
 @pytest.mark.parametrize("name,precs", [
-    ("t-gamma-mix-n48-t100000", ["f64", "f32", "bf16x3", "bf16x2"]),
-    ("laplace-mix-n24-t200000", ["f64", "bf16x2", "bf16x3", "f32"]),
-    ("ar1-garch-n64-t50000", ["f64", "f32", "bf16x3"]),
+    ("t-gamma-mix-n48-t100000", ["f64", "f32", "bf16x3", "bf16x2", "f16x2"]),
+    ("laplace-mix-n24-t200000", ["f64", "bf16x2", "bf16x3", "f32", "f16x2"]),
+    ("ar1-garch-n64-t50000", ["f64", "f32", "bf16x3", "f16x2"]),
 ])
 def test_workload_full_size(dev, orc, name, precs):
     torch, pc = dev
@@ -107,10 +107,10 @@ def test_largest_n(dev, orc):
     X = workloads.t_gamma_mix(t=t, n=n, seed=21)
     Xd = torch.from_numpy(X).cuda()
     K = {}
-    for p in ["f64", "f32", "bf16x3"]:
+    for p in ["f64", "f32", "bf16x3", "f16x2"]:
         _, k = pc.cumulants(Xd, dmax, b, p)
         K[p] = {d: k[d].cpu().numpy() for d in k}
     _, Xc = orc.center(X)
-    sampled_check(pc, orc, Xc, K, n, dmax, b, ["f64", "f32", "bf16x3"], count=400, seed=3)
+    sampled_check(pc, orc, Xc, K, n, dmax, b, ["f64", "f32", "bf16x3", "f16x2"], count=400, seed=3)
     with pytest.raises(pc.CumulantError):
         pc.cumulants(torch.zeros((10, 113), dtype=torch.float64, device="cuda"), 4, 4, "f32")

@@ -8,7 +8,11 @@ entries of order d):
   * BF16x2 path: 5e-5 (each Khatri-Rao operand is carried as two BF16 terms,
     16 significant bits: a relative residual of up to 2^-18 per operand, which
     near-cancelling entries such as the third cumulant of nearly symmetric
-    data amplify), and bit-exact on small-integer data.
+    data amplify), and bit-exact on small-integer data;
+  * FP16x2 path (FP16 hi and 2^11-scaled lo, 22 bits per operand, after a
+    per-variable power-of-two scaling): 1e-6, and bit-exact on small-integer
+    data.  It is a cum_cumulants precision only (orders up to 6; from order 7
+    on every call stages in FP64): moment_blocks, batches and streams refuse it.
 """
 import sys
 
@@ -20,7 +24,8 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 PRECS = ["f64", "f32", "bf16x2", "bf16x3"]
-TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
+CPRECS = PRECS + ["f16x2"]  # precisions of cum_cumulants
+TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6, "f16x2": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -66,7 +71,7 @@ def stored_sample(orc, n, d, b, count, seed):
 
 
 # ---------------------------------------------------------------- exact data
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", CPRECS)
 @pytest.mark.parametrize("n,b,shift", [(6, 4, 0.0), (5, 2, 3.0), (9, 3, -2.0)])
 def test_integer_data_bit_exact(dev, orc, prec, n, b, shift):
     say(f"integer bit-exact prec={prec} n={n} b={b} shift={shift}")
@@ -79,7 +84,7 @@ def test_integer_data_bit_exact(dev, orc, prec, n, b, shift):
         assert np.array_equal(K[d], want), (d, np.abs(K[d] - want).max())
 
 
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", CPRECS)
 @pytest.mark.parametrize("n,b,dmax", [(9, 4, 5), (7, 3, 6), (10, 5, 4)])
 def test_inner_block_sizes_integer_exact(dev, orc, prec, n, b, dmax):
     """Every inner block size of the contraction gives the exact cumulants."""
@@ -101,7 +106,7 @@ def test_inner_block_sizes_integer_exact(dev, orc, prec, n, b, dmax):
         pc.set_tuning(t, n, dmax, b, prec, "32x64", 1024, inner_b=b + 1)
 
 
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", CPRECS)
 def test_unfold_integer_exact(dev, orc, prec):
     torch, pc = dev
     say(f"unfold prec={prec}")
@@ -115,7 +120,7 @@ def test_unfold_integer_exact(dev, orc, prec):
 
 
 # ---------------------------------------------------------------- small dense
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", CPRECS)
 def test_t_wishart_n16_dense(dev, orc, prec):
     say(f"t-wishart n16 t5000 dense prec={prec}")
     X = workloads.generate("t-wishart-n16-t5000")
@@ -128,7 +133,7 @@ def test_t_wishart_n16_dense(dev, orc, prec):
         assert e <= TOL[prec], (d, e)
 
 
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", CPRECS)
 # (9, 8) at d = 6 and (34, 34) at d = 4 hold too many lower-order entries per
 # block to stage them in LDS: the recursion reads them from memory
 @pytest.mark.parametrize("n,b,t,dmax", [(7, 3, 3000, 6), (11, 4, 2000, 5), (13, 13, 1500, 4), (9, 1, 1000, 4),
@@ -173,10 +178,23 @@ def test_moment_blocks_multi_tile_sampled(dev, orc, prec):
             assert not np.any(M[all_offs[~real]])
 
 
+def test_f16x2_refused_outside_cumulants(dev):
+    """The FP16 split scales the data it centres itself, so the calls that take
+    centred data or keep sums across calls refuse it (CUM_EUNSUPPORTED)."""
+    torch, pc = dev
+    Xd = torch.from_numpy(workloads.t_gamma_mix(t=1000, n=6, seed=2)).cuda()
+    with pytest.raises(pc.CumulantError):
+        pc.moment_blocks(Xd.float(), 3, 2, "f16x2")
+    with pytest.raises(pc.CumulantError):
+        pc.Batch([100, 200], 6, 4, 2, "f16x2")
+    with pytest.raises(pc.CumulantError):
+        pc.Stream(6, 4, 2, "f16x2")
+
+
 # ---------------------------------------------------------------- properties
 def test_deterministic_and_shift_invariant(dev):
     X = workloads.t_gamma_mix(t=20_000, n=20, seed=1)
-    for prec in PRECS:
+    for prec in CPRECS:
         say(f"determinism prec={prec}")
         _, K1 = run_gpu(dev, X, 5, 4, prec)
         _, K2 = run_gpu(dev, X, 5, 4, prec)
@@ -236,7 +254,7 @@ def test_autotune_and_tuned_configs(dev, orc):
     _, Xc = orc.center(X)
     offs_idx = {d: stored_sample(orc, 24, d, 4, 200, seed=d) for d in range(2, 6)}
     want = {d: orc.cumulant_at(Xc, offs_idx[d][1]) for d in offs_idx}
-    for prec in PRECS:
+    for prec in CPRECS:
         for bi in [4, 2, 1]:
             for shape in ["32x32", "32x64"]:
                 for target in [256, 1024, 4096]:
@@ -256,7 +274,7 @@ def test_autotune_and_tuned_configs(dev, orc):
         pc.set_tuning(30_000, 24, 5, 4, prec, None)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16x2"])
 def test_graph_capture_replays(dev, orc, prec):
     """After one call of a shape, cum_cumulants allocates nothing and issues
     only kernels, so it can be captured in a HIP graph: every replay (with

@@ -18,11 +18,11 @@ from errmeasure import bound, e_d
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
+TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6, "f16x2": 1e-6}
 PRECS = ["f64", "f32", "bf16x2", "bf16x3"]
 
 
-def cases(count=30, seed=1701):
+def cases(count=30, seed=1701, precs=None):
     rng = np.random.default_rng(seed)
     out = []
     while len(out) < count:
@@ -32,7 +32,7 @@ def cases(count=30, seed=1701):
             continue
         b = int(rng.integers(1, n + 1))
         t = int(rng.choice([1, 2, 3, 63, 64, 65, 500, 1777, 3000]))
-        prec = PRECS[int(rng.integers(0, 4))]
+        prec = PRECS[int(rng.integers(0, 4))] if precs is None else precs[int(rng.integers(0, len(precs)))]
         inner = int(rng.integers(1, b + 1))
         shape = ["32x32", "32x64"][int(rng.integers(0, 2))]
         target = int(rng.choice([64, 1024, 16384]))
@@ -51,7 +51,8 @@ def dev():
     return torch, pc
 
 
-@pytest.mark.parametrize("n,b,d_max,t,prec,inner,shape,target,seed", cases())
+@pytest.mark.parametrize("n,b,d_max,t,prec,inner,shape,target,seed",
+                         cases() + cases(count=12, seed=1716, precs=["f16x2"]))
 def test_random_configuration(dev, orc, n, b, d_max, t, prec, inner, shape, target, seed):
     torch, pc = dev
     print(f"case n={n} b={b} d_max={d_max} t={t} prec={prec} inner_b={inner} {shape} {target}",

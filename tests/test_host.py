@@ -254,7 +254,7 @@ def test_orders_7_and_above_stage_in_fp64(pc):
     in FP64 in every precision: its workspace and its plan are those of the
     FP64 call, while d_max = 6 keeps the precision asked for."""
     t, n, b = 20_000, 8, 2
-    for prec in ("f32", "bf16x2", "bf16x3"):
+    for prec in ("f32", "bf16x2", "bf16x3", "f16x2"):
         for dmax in (7, 10):
             assert pc.workspace_size(t, n, dmax, b, prec) == pc.workspace_size(t, n, dmax, b, "f64")
             assert pc.plan_info(t, n, dmax, b, prec) == pc.plan_info(t, n, dmax, b, "f64")

@@ -26,6 +26,7 @@ def dev():
 @pytest.mark.parametrize("n,b,dmax,prec,sizes", [
     (16, 2, 5, "f32", (30_000, 9_000)),
     (13, 3, 4, "bf16x3", (20_000, 777)),
+    (11, 4, 6, "f16x2", (25_000, 4_000)),
     (8, 2, 8, "f32", (12_000, 3_001)),   # d_max >= 7: staged in FP64, lower central moments in the scratch
 ])
 def test_noalloc_matches_cumulants(dev, n, b, dmax, prec, sizes):
