@@ -35,10 +35,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cumulants d=4..6: eff. TFLOP/s + MFMA util, FP64 vs mixed at stated rel error"
 # MI355X dense matrix-core peaks, TFLOP/s
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "bf16x3": 2500.0}
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "bf16x3": 2500.0, "f16x2": 2500.0}
 # matrix-core products issued per algorithmic multiply-add
-PRODUCTS = {"f64": 1, "f32": 1, "bf16x2": 4, "bf16x3": 6}
-DTYPE = {"f64": "f64", "f32": "f32", "bf16x2": "bf16x2(f32 acc)", "bf16x3": "bf16x3(f32 acc)"}
+PRODUCTS = {"f64": 1, "f32": 1, "bf16x2": 4, "bf16x3": 6, "f16x2": 3}
+DTYPE = {"f64": "f64", "f32": "f32", "bf16x2": "bf16x2(f32 acc)", "bf16x3": "bf16x3(f32 acc)", "f16x2": "f16x2(f32 acc)"}
 
 
 def log(*a):
@@ -305,11 +305,11 @@ def bench_batched(torch, pc, prec, steps, warmup, tune):
 
 def bench_workloads(torch, pc, steps, tune):
     """The higher-order workloads (d_max = 6 and 5) in every precision (FP32,
-    FP64 and the two- and three-term BF16 splits): step time, effective
+    FP64, the two- and three-term BF16 splits and the FP16 split): step time, effective
     throughput (the block method's FLOP, 2 t sum_d stored_d) and the same
     time against the distinct-tuple lower bound (2 t sum_d C(n+d-1, d)),
     moment-kernel throughput and matrix-unit fraction (issued products:
-    4 or 6 per FMA for the BF16 splits), and e_d per order against the
+    4 or 6 per FMA for the BF16 splits, 3 for the FP16 split), and e_d per order against the
     oracle's stored values at about 300 sampled entries per order (random
     positions, every pure diagonal, and copies in blocks with repeated block
     indices)."""
@@ -325,7 +325,7 @@ def bench_workloads(torch, pc, steps, tune):
         flops = alg_flops(pc, t, n, d_max, b)
         uflops = alg_flops(pc, t, n, d_max, 1)
         res, kap = {}, {}
-        for p in ["f32", "f64", "bf16x3", "bf16x2"]:
+        for p in ["f32", "f64", "bf16x3", "bf16x2", "f16x2"]:
             wall, kinds, o, tuned, pct = time_path(torch, pc, Xd, d_max, b, p, steps, 2, tune)
             cfg = pc.get_tuning(t, n, d_max, b, p)
             kflops = alg_flops(pc, t, n, d_max, cfg["inner_b"])
@@ -507,7 +507,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="t-gamma-mix-n48-t100000")
     ap.add_argument("--prec", default="f32", help="precision of the reported path")
-    ap.add_argument("--compare", default="f64,bf16x3,bf16x2", help="further precisions timed on the same data")
+    ap.add_argument("--compare", default="f64,bf16x3,bf16x2,f16x2", help="further precisions timed on the same data")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
