@@ -139,7 +139,8 @@ cum_status cum_center(const double *X, int64_t t, int n, int64_t ldx, cum_prec p
  *   Xc  t x n, leading dimension n, FP64 for CUM_F64, FP32 otherwise
  *   M   cum_layout.elems FP64 out
  * Requires t >= 1, 1 <= b <= n, 2 <= d <= CUM_MAX_ORDER.  Results are
- * deterministic: the same call gives bitwise the same output. */
+ * deterministic: the same call gives bitwise the same output.  CUM_F16X2 is
+ * refused (CUM_EUNSUPPORTED): its scaling needs the data's centring. */
 cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, int d, int b, double *M, void *ws,
                              size_t ws_bytes, void *stream);
 
@@ -269,7 +270,7 @@ cum_status cum_get_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, cum
 typedef struct cum_batch cum_batch;
 
 /* Host only (allocates the plan's device memory).  t_i (host, n_sets
- * entries, each >= 1). */
+ * entries, each >= 1).  CUM_F16X2 is refused (CUM_EUNSUPPORTED). */
 cum_status cum_batch_create(int n_sets, const int64_t *t_i /* host */, int n, int d_max, int b, cum_prec prec,
                             cum_batch **plan /* host out */);
 
@@ -315,7 +316,8 @@ cum_status cum_batch_destroy(cum_batch *plan);
 typedef struct cum_stream cum_stream;
 
 /* Host only (allocates the stream's device memory).  shift (host, n values)
- * or NULL: the mean of the first batch added becomes the shift. */
+ * or NULL: the mean of the first batch added becomes the shift.  CUM_F16X2
+ * is refused (CUM_EUNSUPPORTED). */
 cum_status cum_stream_create(int n, int d_max, int b, cum_prec prec, const double *shift /* host */,
                              cum_stream **stream_out /* host out */);
 
