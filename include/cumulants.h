@@ -90,8 +90,8 @@ typedef enum {
                     /* FP16 hi and lo * 2^11 (22 bits), the 3 cross products   */
                     /* hh, hl, lh on FP16 matrix cores, FP32 sums over at most */
                     /* 64 samples, then FP64, the powers of two undone exactly */
-                    /* (orders 2..6; cum_cumulants, its no-allocation variant  */
-                    /* and cum_autotune only: elsewhere CUM_EUNSUPPORTED)      */
+                    /* (orders 2..6; cum_cumulants, its no-allocation variant, */
+                    /* cum_autotune and batches: elsewhere CUM_EUNSUPPORTED)   */
     /* Not precisions: these give the enum the range of int32_t, so that an
      * unknown value is a valid cum_prec object that the library rejects with
      * CUM_EUNSUPPORTED (without them, reading one is undefined in C++). */
@@ -270,7 +270,7 @@ cum_status cum_get_tuning(int64_t t, int n, int d_max, int b, cum_prec prec, cum
 typedef struct cum_batch cum_batch;
 
 /* Host only (allocates the plan's device memory).  t_i (host, n_sets
- * entries, each >= 1).  CUM_F16X2 is refused (CUM_EUNSUPPORTED). */
+ * entries, each >= 1).  With CUM_F16X2 each dataset has its own scales. */
 cum_status cum_batch_create(int n_sets, const int64_t *t_i /* host */, int n, int d_max, int b, cum_prec prec,
                             cum_batch **plan /* host out */);
 

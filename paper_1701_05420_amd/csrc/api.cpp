@@ -995,6 +995,7 @@ static cum_status run_contraction(const Call &k, const void *Xc, double *partial
     ma.raw = raw ? partial : nullptr;
     ma.rawstride = rs;
     ma.scale = scale;
+    ma.set0.scale = scale;
     *sums = partial;
     if (nitems > 0)
         HIP_TRY(timed(CUM_KIND_MOMENT, s, [&] { return launch_moment(c->prec, c->shape, c->dhi, ma, (int)nitems, s); }));
@@ -1791,7 +1792,7 @@ struct cum_batch {
     std::vector<CenterSet> csets;
     int max_groups = 1, stage_blocks = 1;
     DevBuf ords_d, tiles_d, items_d, red_d, sets_d, setred_d, cset_d;
-    DevBuf staged_d, partial_d, part_d, mean_d, stamps_d;
+    DevBuf staged_d, partial_d, part_d, mean_d, stamps_d, mm_d, scale_d;
     CenterSet *h_cset = nullptr;  // pinned staging of the per-run pointer tables
     SetRed *h_setred = nullptr;
     hipEvent_t copied = nullptr, done = nullptr, ready = nullptr;
@@ -1985,8 +1986,8 @@ static cum_status batch_layout(cum_batch &p, int bi, int shape, int target) {
 static cum_status batch_enqueue(cum_batch &p, hipStream_t s) {
     HIP_TRY(launch_batch_stamp((unsigned long long *)p.stamps_d.p, p.nsets, s));
     const CenterSet *cs = (const CenterSet *)p.cset_d.p;
-    HIP_TRY(launch_batch_colsum(cs, p.nsets, p.max_groups, p.n, s));
-    HIP_TRY(launch_batch_mean(cs, p.nsets, p.n, s));
+    HIP_TRY(launch_batch_colsum(cs, p.nsets, p.max_groups, p.n, s, p.prec == CUM_F16X2));
+    HIP_TRY(launch_batch_mean(cs, p.nsets, p.n, s, p.prec == CUM_F16X2));
     HIP_TRY(launch_batch_stage(cs, p.nsets, p.n, p.prec, p.stage_blocks, s));
     const RedOrder *red_d = (const RedOrder *)p.red_d.p;
     const SetRed *setred = (const SetRed *)p.setred_d.p;
@@ -2040,7 +2041,6 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
     *plan = nullptr;
     if (n_sets < 1 || n_sets > 65535) return fail(CUM_EINVAL, "n_sets must be in 1..65535");
     if ((st = check_common(1, n, b)) || (st = check_prec(prec))) return st;
-    if (prec == CUM_F16X2) return fail(CUM_EUNSUPPORTED, "batches and streams do not take the FP16 split");
     if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
     prec = (cum_prec)staged_prec(prec, d_max);
     for (int s = 0; s < n_sets; ++s)
@@ -2090,6 +2090,11 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
     }
     HIP_TRY(hipMalloc(&p->staged_d.p, std::max<int64_t>(staged, 256)));
     HIP_TRY(hipMalloc(&p->part_d.p, std::max<int64_t>(parts, 1) * sizeof(double)));
+    if (prec == CUM_F16X2) {
+        // each dataset's column minima / maxima (laid out as its partial sums) and scales
+        HIP_TRY(hipMalloc(&p->mm_d.p, std::max<int64_t>(parts, 1) * sizeof(double)));
+        HIP_TRY(hipMalloc(&p->scale_d.p, (size_t)n_sets * (n + 1) * sizeof(double)));
+    }
     HIP_TRY(hipMalloc(&p->mean_d.p, (size_t)n_sets * n * sizeof(double)));
     HIP_TRY(hipMalloc(&p->stamps_d.p, (size_t)(n_sets + 1) * sizeof(unsigned long long)));
     for (int s = 0; s < n_sets; ++s) {
@@ -2099,7 +2104,10 @@ cum_status cum_batch_create(int n_sets, const int64_t *t_i, int n, int d_max, in
         c.Xc = (char *)p->staged_d.p + st_off[s];
         c.part = (double *)p->part_d.p + part_off[s];
         c.pad = 0;
+        c.mm = p->mm_d.p ? (double *)p->mm_d.p + part_off[s] : nullptr;
+        c.scale = p->scale_d.p ? (double *)p->scale_d.p + (int64_t)s * (n + 1) : nullptr;
         p->sets[s].X = c.Xc;
+        p->sets[s].scale = c.scale;
         SetRed &r = p->setred[s];
         r.t = p->t[s];
         for (int k = 0; k < MAXD - 1; ++k) r.kappa[k] = r.mom[k] = nullptr;
@@ -2313,7 +2321,7 @@ cum_status cum_stream_create(int n, int d_max, int b, cum_prec prec, const doubl
     if (!out) return fail(CUM_EINVAL, "NULL argument");
     *out = nullptr;
     if ((st = check_common(1, n, b)) || (st = check_prec(prec))) return st;
-    if (prec == CUM_F16X2) return fail(CUM_EUNSUPPORTED, "batches and streams do not take the FP16 split");
+    if (prec == CUM_F16X2) return fail(CUM_EUNSUPPORTED, "streams do not take the FP16 split");
     if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
     prec = (cum_prec)staged_prec(prec, d_max);
     for (int d = 2; d <= d_max; ++d)

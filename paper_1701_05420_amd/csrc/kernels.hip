@@ -201,15 +201,17 @@ __global__ __launch_bounds__(256) void center_kernel(const double *X, int64_t t,
     }
 }
 
+template <bool MM>
 __global__ __launch_bounds__(256) void batch_colsum_kernel(const CenterSet *sets, int n) {
     const CenterSet cs = sets[blockIdx.y];
     if ((int)blockIdx.x >= cs.groups) return;
-    colsum_body(cs.X, cs.t, n, n, cs.rows_per, blockIdx.x, cs.part);
+    colsum_body<MM>(cs.X, cs.t, n, n, cs.rows_per, blockIdx.x, cs.part, cs.mm);
 }
 
+template <bool MM>
 __global__ __launch_bounds__(256) void batch_mean_kernel(const CenterSet *sets, int n) {
     const CenterSet cs = sets[blockIdx.y];
-    mean_body(cs.part, cs.groups, n, cs.t, cs.mean, blockIdx.x);
+    mean_body<MM>(cs.part, cs.groups, n, cs.t, cs.mean, blockIdx.x, cs.mm, cs.scale);
 }
 
 __global__ void stamp_kernel(unsigned long long *where) {
@@ -297,17 +299,21 @@ hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const doub
 
 // Batched: grid (blocks per dataset, datasets); each block walks its
 // dataset's stages with stride gridDim.x.
-template <typename TO>
+template <typename TO, bool SCALED = false>
 __global__ __launch_bounds__(256) void batch_stage_kernel(const CenterSet *sets, int n, int KT, int KTP) {
     const CenterSet cs = sets[blockIdx.y];
     const int64_t nst = (cs.t + KT - 1) / KT;
     for (int64_t st = blockIdx.x; st < nst; st += gridDim.x)
-        stage_body<double, TO, true>(cs.X, cs.t, n, n, cs.mean, reinterpret_cast<TO *>(cs.Xc), KT, KTP, st);
+        stage_body<double, TO, true, SCALED>(cs.X, cs.t, n, n, cs.mean, reinterpret_cast<TO *>(cs.Xc), KT, KTP, st,
+                                             cs.scale);
 }
 
 hipError_t launch_batch_stage(const CenterSet *sets, int nsets, int n, int prec, int blocks_per_set, hipStream_t s) {
     const int KT = stage_kt(prec), KTP = stage_pitch(prec);
-    if (prec == P_F64)
+    if (prec == P_F16X2)
+        hipLaunchKernelGGL((batch_stage_kernel<float, true>), dim3(blocks_per_set, nsets), dim3(256), 0, s, sets, n, KT,
+                           KTP);
+    else if (prec == P_F64)
         hipLaunchKernelGGL(batch_stage_kernel<double>, dim3(blocks_per_set, nsets), dim3(256), 0, s, sets, n, KT, KTP);
     else
         hipLaunchKernelGGL(batch_stage_kernel<float>, dim3(blocks_per_set, nsets), dim3(256), 0, s, sets, n, KT, KTP);
@@ -766,6 +772,7 @@ __device__ __forceinline__ void moment_item(const Item &item, const TileDev *til
     if constexpr (F16) {
         // undo the staging's per-variable powers of two (exact): each sum of
         // products of row and column operands times the scales of their variables
+        if (!scale) scale = sd.scale;  // batches: each dataset's own
         double cs[WN][2], rs[2][4];
 #pragma unroll
         for (int j = 0; j < WN; ++j)
@@ -958,7 +965,7 @@ hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int
         case P_F32: return launch_moment_prec<P_F32>(shape, dmax, a, grid, s);
         case P_BF16X2: return launch_moment_prec<P_BF16X2>(shape, dmax, a, grid, s);
         case P_F16X2:
-            if (dmax > 6 || !a.scale) return hipErrorInvalidValue;
+            if (dmax > 6 || (!a.scale && !a.sets)) return hipErrorInvalidValue;
             return launch_moment_prec<P_F16X2>(shape, dmax, a, grid, s);
         default: return launch_moment_prec<P_BF16X3>(shape, dmax, a, grid, s);
     }
@@ -2249,13 +2256,19 @@ hipError_t launch_center(const double *X, int64_t t, int n, int64_t ldx, const d
     return hipGetLastError();
 }
 
-hipError_t launch_batch_colsum(const CenterSet *sets, int nsets, int max_groups, int n, hipStream_t s) {
-    hipLaunchKernelGGL(batch_colsum_kernel, dim3(max_groups, nsets), dim3(256), 0, s, sets, n);
+hipError_t launch_batch_colsum(const CenterSet *sets, int nsets, int max_groups, int n, hipStream_t s, bool mm) {
+    if (mm)
+        hipLaunchKernelGGL(batch_colsum_kernel<true>, dim3(max_groups, nsets), dim3(256), 0, s, sets, n);
+    else
+        hipLaunchKernelGGL(batch_colsum_kernel<false>, dim3(max_groups, nsets), dim3(256), 0, s, sets, n);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_mean(const CenterSet *sets, int nsets, int n, hipStream_t s) {
-    hipLaunchKernelGGL(batch_mean_kernel, dim3(n, nsets), dim3(256), 0, s, sets, n);
+hipError_t launch_batch_mean(const CenterSet *sets, int nsets, int n, hipStream_t s, bool mm) {
+    if (mm)
+        hipLaunchKernelGGL(batch_mean_kernel<true>, dim3(n, nsets), dim3(256), 0, s, sets, n);
+    else
+        hipLaunchKernelGGL(batch_mean_kernel<false>, dim3(n, nsets), dim3(256), 0, s, sets, n);
     return hipGetLastError();
 }
 

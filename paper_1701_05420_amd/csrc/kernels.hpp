@@ -119,9 +119,11 @@ struct CenterSet {
     int32_t groups;
     int32_t pad;
     int64_t rows_per;
+    double *mm;        // FP16 split: groups x n x 2 column minima and maxima, else null
+    double *scale;     // FP16 split: n + 1 powers of two (see launch_mean), else null
 };
-hipError_t launch_batch_colsum(const CenterSet *sets, int nsets, int max_groups, int n, hipStream_t s);
-hipError_t launch_batch_mean(const CenterSet *sets, int nsets, int n, hipStream_t s);
+hipError_t launch_batch_colsum(const CenterSet *sets, int nsets, int max_groups, int n, hipStream_t s, bool mm = false);
+hipError_t launch_batch_mean(const CenterSet *sets, int nsets, int n, hipStream_t s, bool mm = false);
 hipError_t launch_batch_stage(const CenterSet *sets, int nsets, int n, int prec, int blocks_per_set, hipStream_t s);
 hipError_t launch_batch_stamp(unsigned long long *stamps, int nsets, hipStream_t s);
 hipError_t launch_stamp(unsigned long long *where, hipStream_t s);

@@ -103,6 +103,8 @@ struct SetDev {
     int64_t nchunks;
     double *partial;       // nchunks x stride
     int64_t stride;        // stored entries of all orders 2..d_max
+    const double *scale;   // FP16 split: the powers of two the staged rows were divided by
+                           // (n + 1), else null
 };
 
 // Reduction / recursion records.

@@ -10,7 +10,7 @@ from errmeasure import bound, e_d
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
+TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6, "f16x2": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -33,7 +33,7 @@ def rel(got, want):
     return np.abs(got - want).max() / (den if den > 0 else 1.0)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3", "f16x2"])
 def test_batch_matches_oracle_and_replays(dev, orc, prec):
     torch, pc = dev
     n, b, dmax = 13, 4, 5
@@ -73,7 +73,7 @@ def test_batch_integer_exact_and_autotune(dev, orc):
     ts = [64, 128, 256, 32, 512]
     Xs = [workloads.dyadic_integers(t=t, n=n, seed=t, lo=-2, hi=2) for t in ts]
     Xd = [torch.from_numpy(X).cuda() for X in Xs]
-    for prec in ["f64", "f32", "bf16x2", "bf16x3"]:
+    for prec in ["f64", "f32", "bf16x2", "bf16x3", "f16x2"]:
         say(f"batch integer prec={prec}")
         batch = pc.Batch(ts, n, dmax, b, prec)
         best = batch.autotune(Xd)

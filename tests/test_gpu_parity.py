@@ -11,8 +11,8 @@ entries of order d):
     data amplify), and bit-exact on small-integer data;
   * FP16x2 path (FP16 hi and 2^11-scaled lo, 22 bits per operand, after a
     per-variable power-of-two scaling): 1e-6, and bit-exact on small-integer
-    data.  It is a cum_cumulants precision only (orders up to 6; from order 7
-    on every call stages in FP64): moment_blocks, batches and streams refuse it.
+    data.  Orders up to 6 (from order 7 on every call stages in FP64); single
+    calls and batches take it, moment_blocks and streams refuse it.
 """
 import sys
 
@@ -185,8 +185,6 @@ def test_f16x2_refused_outside_cumulants(dev):
     Xd = torch.from_numpy(workloads.t_gamma_mix(t=1000, n=6, seed=2)).cuda()
     with pytest.raises(pc.CumulantError):
         pc.moment_blocks(Xd.float(), 3, 2, "f16x2")
-    with pytest.raises(pc.CumulantError):
-        pc.Batch([100, 200], 6, 4, 2, "f16x2")
     with pytest.raises(pc.CumulantError):
         pc.Stream(6, 4, 2, "f16x2")
 
