@@ -248,9 +248,10 @@ def cpu_oracle_configs(orc, pc):
     return out
 
 
-def bench_batched(torch, pc, prec, steps, warmup, tune):
+def bench_batched(torch, pc, prec, steps, warmup, tune, per_dataset=True):
     """The 512-dataset workload: one graph replay per step vs one
-    cum_cumulants call per dataset; datasets/s and per-dataset latency."""
+    cum_cumulants call per dataset (unless per_dataset is false); datasets/s
+    and per-dataset latency."""
     import workloads
 
     name = "batch512-t-corr-n32"
@@ -277,6 +278,13 @@ def bench_batched(torch, pc, prec, steps, warmup, tune):
     start, ticks, hz = batch.timestamps()
     lat = np.array([(tk - start) / hz * 1e3 for tk in ticks])
     batch.close()
+    rec = {"workload": name, "n_sets": len(ts), "prec": prec, "t_total": int(sum(ts)),
+           "ms_per_batch": ms, "datasets_per_s": len(ts) / ms * 1e3, "eff_tflops": flops / (ms * 1e-3) / 1e12,
+           "tflops_unique": uflops / (ms * 1e-3) / 1e12,
+           "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+           "tuning": tuned}
+    if not per_dataset:
+        return rec
     # one launch sequence per dataset, same precision, buffers preallocated
     wsz = max(pc.workspace_size(t, n, d_max, b, prec) for t in ts)
     ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
@@ -293,14 +301,10 @@ def bench_batched(torch, pc, prec, steps, warmup, tune):
     torch.cuda.synchronize()
     seq_ms = (time.perf_counter() - t0) * 1e3
     seq_lat = np.array([ev0.elapsed_time(e) for e in evs])
-    return {"workload": name, "n_sets": len(ts), "prec": prec, "t_total": int(sum(ts)),
-            "ms_per_batch": ms, "datasets_per_s": len(ts) / ms * 1e3, "eff_tflops": flops / (ms * 1e-3) / 1e12,
-            "tflops_unique": uflops / (ms * 1e-3) / 1e12,
-            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
-            "per_dataset_calls": {"ms_total": seq_ms, "datasets_per_s": len(ts) / seq_ms * 1e3,
-                                  "latency_ms_p50": float(np.percentile(seq_lat, 50)),
-                                  "latency_ms_p99": float(np.percentile(seq_lat, 99))},
-            "tuning": tuned}
+    rec["per_dataset_calls"] = {"ms_total": seq_ms, "datasets_per_s": len(ts) / seq_ms * 1e3,
+                                "latency_ms_p50": float(np.percentile(seq_lat, 50)),
+                                "latency_ms_p99": float(np.percentile(seq_lat, 99))}
+    return rec
 
 
 def bench_workloads(torch, pc, steps, tune):
@@ -620,6 +624,9 @@ def main():
         line["batched"] = bench_batched(torch, pc, main_p, max(3, args.steps // 4), 1, not args.no_tune)
         log(f"  batched: {line['batched']['datasets_per_s']:.0f} datasets/s vs "
             f"{line['batched']['per_dataset_calls']['datasets_per_s']:.0f} with one call per dataset")
+        line["batched"]["other_precisions"] = {
+            "f16x2": bench_batched(torch, pc, "f16x2", max(3, args.steps // 4), 1, not args.no_tune, per_dataset=False)}
+        log(f"  batched f16x2: {line['batched']['other_precisions']['f16x2']['datasets_per_s']:.0f} datasets/s")
     if not args.no_streaming:
         log("streaming window")
         sw = bench_streaming(torch, pc, X, n, d_max, b, main_p, max(5, args.steps // 2))
