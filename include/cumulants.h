@@ -85,9 +85,10 @@ typedef enum {
                     /* over at most 64 samples, then FP64                       */
     CUM_BF16X3 = 3, /* as BF16X2 with a three-term split and the 6 cross       */
                     /* products of combined weight >= 2^-16                     */
-    CUM_F16X2 = 4,  /* FP32 data, each variable first divided by a power of    */
-                    /* two that bounds it by 32; each half-product split into  */
-                    /* FP16 hi and lo * 2^11 (22 bits), the 3 cross products   */
+    CUM_F16X2 = 4,  /* FP32 data, each variable's centred values first divided */
+                    /* by a power of two that brings them below 32; each half- */
+                    /* product v split into FP16 hi and lo = (v - hi) * 2^11   */
+                    /* rounded to FP16 (22 bits of v), the 3 cross products    */
                     /* hh, hl, lh on FP16 matrix cores, FP32 sums over at most */
                     /* 64 samples, then FP64, the powers of two undone exactly */
                     /* (orders 2..6; cum_cumulants, its no-allocation variant, */
