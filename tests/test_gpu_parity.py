@@ -20,6 +20,7 @@ import numpy as np
 import pytest
 
 import workloads
+from errmeasure import bound
 
 pytestmark = pytest.mark.gpu
 
@@ -187,6 +188,42 @@ def test_f16x2_refused_outside_cumulants(dev):
         pc.moment_blocks(Xd.float(), 3, 2, "f16x2")
     with pytest.raises(pc.CumulantError):
         pc.Stream(6, 4, 2, "f16x2")
+
+
+def test_f16x2_scaling_extremes(dev, orc):
+    """The FP16 split's per-variable powers of two: columns 2^-40 .. 2^40
+    apart, a far outlier, a constant column and data far from zero.  With
+    every entry divided by its variables' column scales (exact powers of two),
+    e_d stays within the FP32-staged bound; each variable's own cumulants (the
+    pure diagonal) are within 1e-6 of the oracle relative to themselves,
+    times max(1, |m_d| / |c_d|) for the cancellation in c_d; all finite."""
+    torch, pc = dev
+    n, b, dmax, t = 7, 3, 6, 3000
+    cs = np.ldexp(1.0, np.array([-40, -13, 0, 7, 21, 40, 0]))
+    X = workloads.t_gamma_mix(t=t, n=n, seed=77) * cs[None, :]
+    X[123, 2] += 200.0 * np.abs(X[:, 2]).max()  # one far outlier
+    X[:, 6] = 5.0                                 # a constant column
+    X = X + 1e3 * cs[None, :]                     # far from zero
+    say("f16x2 scaling extremes")
+    _, K = run_gpu(dev, X, dmax, b, "f16x2")
+    _, OK = orc.cumulants_dense(X, dmax)
+    Xc = X - X.mean(axis=0)
+    for d in range(2, dmax + 1):
+        got, want = K[d], orc.fold(OK[d], b)
+        assert np.all(np.isfinite(got)), d
+        idx = orc.block_indices(n, d, b, np.arange(got.size))
+        real = idx[:, 0] >= 0
+        norm = np.ones(got.size)
+        norm[real] = np.prod(cs[idx[real]], axis=1)
+        e = rel(got / norm, want / norm)
+        tol = bound(TOL["f16x2"], "f16x2", t, orc, Xc / cs[None, :], orc.fold(OK[d], b) / norm, d)
+        say(f"  e_{d} (scaled) = {e:.3e} (tolerance {tol:.3e})")
+        assert e <= tol, (d, e, tol)
+        for i in range(n - 1):
+            off = pc.stored_offset(n, d, b, [i] * d)
+            m = np.mean(Xc[:, i] ** d)
+            w = want[off]
+            assert abs(got[off] - w) <= 1e-6 * max(abs(w), abs(m)), (i, d, got[off], w, m)
 
 
 # ---------------------------------------------------------------- properties
