@@ -91,8 +91,8 @@ typedef enum {
                     /* rounded to FP16 (22 bits of v), the 3 cross products    */
                     /* hh, hl, lh on FP16 matrix cores, FP32 sums over at most */
                     /* 64 samples, then FP64, the powers of two undone exactly */
-                    /* (orders 2..6; cum_cumulants, its no-allocation variant, */
-                    /* cum_autotune and batches: elsewhere CUM_EUNSUPPORTED)   */
+                    /* (orders 2..6; every call that centres its own data:     */
+                    /* cum_moment_blocks refuses it with CUM_EUNSUPPORTED)      */
     /* Not precisions: these give the enum the range of int32_t, so that an
      * unknown value is a valid cum_prec object that the library rejects with
      * CUM_EUNSUPPORTED (without them, reading one is undefined in C++). */
@@ -317,8 +317,8 @@ cum_status cum_batch_destroy(cum_batch *plan);
 typedef struct cum_stream cum_stream;
 
 /* Host only (allocates the stream's device memory).  shift (host, n values)
- * or NULL: the mean of the first batch added becomes the shift.  CUM_F16X2
- * is refused (CUM_EUNSUPPORTED). */
+ * or NULL: the mean of the first batch added becomes the shift.  With
+ * CUM_F16X2 each batch has its own scales, bounding it about the shift. */
 cum_status cum_stream_create(int n, int d_max, int b, cum_prec prec, const double *shift /* host */,
                              cum_stream **stream_out /* host out */);
 

@@ -2321,7 +2321,6 @@ cum_status cum_stream_create(int n, int d_max, int b, cum_prec prec, const doubl
     if (!out) return fail(CUM_EINVAL, "NULL argument");
     *out = nullptr;
     if ((st = check_common(1, n, b)) || (st = check_prec(prec))) return st;
-    if (prec == CUM_F16X2) return fail(CUM_EUNSUPPORTED, "streams do not take the FP16 split");
     if (d_max < 2 || d_max > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d_max must be in 2..%d", CUM_MAX_ORDER);
     prec = (cum_prec)staged_prec(prec, d_max);
     for (int d = 2; d <= d_max; ++d)
@@ -2388,7 +2387,8 @@ cum_status cum_stream_update(cum_stream *p, const double *X, int64_t t, int64_t 
     int64_t rows_per;
     center_groups(t, groups, rows_per);
     const size_t xbytes = staged_bytes(t, n, p->prec), cbytes = align_up((size_t)groups * n * 2 * 8);
-    const size_t need = xbytes + cbytes + align_up(partial_bytes(k));
+    const size_t pbytes = align_up(partial_bytes(k));
+    const size_t need = xbytes + cbytes + pbytes + f16_bytes(p->prec, groups, n);
     if (need > p->ws_bytes) {
         // the old workspace may still be read by work queued on the stream
         HIP_TRY(hipStreamSynchronize(s));
@@ -2404,7 +2404,20 @@ cum_status cum_stream_update(cum_stream *p, const double *X, int64_t t, int64_t 
     double *partial = (double *)(cw + cbytes);
     double *shift = (double *)p->shift_d.p, *bmean = (double *)p->bmean_d.p;
     // the batch's mean; the first batch's mean becomes the shift if none was given
-    if ((st = center_impl(X, t, n, ldx, p->prec, bmean, nullptr, cw, cbytes, s))) return st;
+    const double *scale = nullptr;
+    if (p->prec == CUM_F16X2) {
+        // this batch's own powers of two, bounding its values about the shift
+        // (about its mean when that becomes the shift); undone in the
+        // contraction, so the window's FP64 sums hold unscaled data
+        char *fw = cw + cbytes + pbytes;
+        double *mm = (double *)fw, *sc = (double *)(fw + align_up((size_t)groups * n * 2 * 8));
+        const double *center = p->have_shift ? shift : nullptr;
+        HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_colsum(X, t, n, ldx, rows_per, groups, (double *)cw, s, mm); }));
+        HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_mean((double *)cw, groups, n, t, bmean, s, mm, sc, center); }));
+        scale = sc;
+    } else if ((st = center_impl(X, t, n, ldx, p->prec, bmean, nullptr, cw, cbytes, s))) {
+        return st;
+    }
     if (!p->have_shift) {
         HIP_TRY(hipMemcpyAsync(shift, bmean, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
         p->have_shift = true;
@@ -2413,10 +2426,12 @@ cum_status cum_stream_update(cum_stream *p, const double *X, int64_t t, int64_t 
         return launch_stream_sum1((double *)p->s1_d.p, bmean, shift, (double)sign * (double)t, n, s);
     }));
     // the batch's sums of products of x - c, added into (or taken from) the window's
-    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] { return launch_stage(X, t, n, ldx, shift, Xst, p->prec, true, true, s); }));
+    HIP_TRY(timed(CUM_KIND_CENTER, s, [&] {
+        return launch_stage(X, t, n, ldx, shift, Xst, p->prec, true, true, s, scale);
+    }));
     bool summed;
     double *sums = nullptr;
-    if ((st = run_contraction(k, Xst, partial, true, &summed, s, &sums))) return st;
+    if ((st = run_contraction(k, Xst, partial, true, &summed, s, &sums, scale))) return st;
     HIP_TRY(timed(CUM_KIND_REDUCE, s,
                   [&] { return launch_axpy((double *)p->sums_d.p, sums, (double)sign, p->stride, s); }));
     p->t += sign * t;

@@ -130,13 +130,15 @@ __global__ __launch_bounds__(256) void colsum_kernel(const double *X, int64_t t,
 // One work-group per column: thread k sums groups k, k+256, ...; the 256
 // compensated partials are then combined pairwise in a fixed tree.
 // MM (the FP16 split): from the groups' minima and maxima, also the power of
-// two scale[i] = 2^(e - 5), where a = max |x - mean| over the column lies in
-// [2^(e-1), 2^e) (scale 1 for a constant column), and scale[n] = 1.  Divided
-// by it, every centred value is below 32 in magnitude, so a product of up to
-// three of them stays below the FP16 maximum (65504).
+// two scale[i] = 2^(e - 5), where a = max |x - c| over the column lies in
+// [2^(e-1), 2^e), c being center[i] if given (the fixed shift a stream stages
+// about) and the mean otherwise (scale 1 where a = 0), and scale[n] = 1.
+// Divided by it, every staged value is below 32 in magnitude, so a product
+// of up to three of them stays below the FP16 maximum (65504).
 template <bool MM = false>
 __device__ __forceinline__ void mean_body(const double *part, int groups, int n, int64_t t, double *mean, int i,
-                                          const double *mm = nullptr, double *scale = nullptr) {
+                                          const double *mm = nullptr, double *scale = nullptr,
+                                          const double *center = nullptr) {
     __shared__ double ss[256], cs[256];
     __shared__ double lo_s[MM ? 256 : 1], hi_s[MM ? 256 : 1];
     const int tid = threadIdx.x;
@@ -173,7 +175,9 @@ __device__ __forceinline__ void mean_body(const double *part, int groups, int n,
         const double mu = (ss[0] + cs[0]) / (double)t;
         mean[i] = mu;
         if constexpr (MM) {
-            const double a = fmax(hi_s[0] - mu, mu - lo_s[0]);
+            // the values are staged about center (a stream's fixed shift) when given
+            const double c = center ? center[i] : mu;
+            const double a = fmax(hi_s[0] - c, c - lo_s[0]);
             int e = 0;
             if (a > 0.0) {
                 (void)frexp(a, &e);  // a = f * 2^e, f in [0.5, 1): 2^e >= a
@@ -186,8 +190,9 @@ __device__ __forceinline__ void mean_body(const double *part, int groups, int n,
 
 template <bool MM>
 __global__ __launch_bounds__(256) void mean_kernel(const double *part, int groups, int n, int64_t t,
-                                                   double *mean, const double *mm, double *scale) {
-    mean_body<MM>(part, groups, n, t, mean, blockIdx.x, mm, scale);
+                                                   double *mean, const double *mm, double *scale,
+                                                   const double *center) {
+    mean_body<MM>(part, groups, n, t, mean, blockIdx.x, mm, scale, center);
 }
 
 template <typename T>
@@ -2235,11 +2240,12 @@ hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t
 }
 
 hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s,
-                       const double *mm, double *scale) {
+                       const double *mm, double *scale, const double *center) {
     if (mm && scale)
-        hipLaunchKernelGGL(mean_kernel<true>, dim3(n), dim3(256), 0, s, part, groups, n, t, mean, mm, scale);
+        hipLaunchKernelGGL(mean_kernel<true>, dim3(n), dim3(256), 0, s, part, groups, n, t, mean, mm, scale, center);
     else
-        hipLaunchKernelGGL(mean_kernel<false>, dim3(n), dim3(256), 0, s, part, groups, n, t, mean, nullptr, nullptr);
+        hipLaunchKernelGGL(mean_kernel<false>, dim3(n), dim3(256), 0, s, part, groups, n, t, mean, nullptr, nullptr,
+                           nullptr);
     return hipGetLastError();
 }
 

@@ -100,11 +100,12 @@ hipError_t launch_recentre(const RecArgs &a, hipStream_t s);
 hipError_t launch_moebius(const MoebArgs &a, hipStream_t s);
 // With mm (groups x n x 2 doubles), the column sums also record each
 // group's column minima and maxima; launch_mean then also writes scale
-// (n + 1 doubles) for the FP16 split: see launch_mean.
+// (n + 1 doubles) for the FP16 split, bounding the values about center
+// (n doubles) when given, else about the mean: see mean_body.
 hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int groups, double *part,
                          hipStream_t s, double *mm = nullptr);
 hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s,
-                       const double *mm = nullptr, double *scale = nullptr);
+                       const double *mm = nullptr, double *scale = nullptr, const double *center = nullptr);
 hipError_t launch_center(const double *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xc, int prec,
                          hipStream_t s);
 hipError_t launch_unfold(const double *blocks, int n, int d, int b, double *dense, hipStream_t s);

@@ -11,8 +11,8 @@ entries of order d):
     data amplify), and bit-exact on small-integer data;
   * FP16x2 path (FP16 hi and 2^11-scaled lo, 22 bits per operand, after a
     per-variable power-of-two scaling): 1e-6, and bit-exact on small-integer
-    data.  Orders up to 6 (from order 7 on every call stages in FP64); single
-    calls and batches take it, moment_blocks and streams refuse it.
+    data.  Orders up to 6 (from order 7 on every call stages in FP64); every
+    call that centres its own data takes it, moment_blocks refuses it.
 """
 import sys
 
@@ -180,14 +180,12 @@ def test_moment_blocks_multi_tile_sampled(dev, orc, prec):
 
 
 def test_f16x2_refused_outside_cumulants(dev):
-    """The FP16 split scales the data it centres itself, so the calls that take
-    centred data or keep sums across calls refuse it (CUM_EUNSUPPORTED)."""
+    """The FP16 split scales the data it centres itself, so the call that takes
+    centred data refuses it (CUM_EUNSUPPORTED)."""
     torch, pc = dev
     Xd = torch.from_numpy(workloads.t_gamma_mix(t=1000, n=6, seed=2)).cuda()
     with pytest.raises(pc.CumulantError):
         pc.moment_blocks(Xd.float(), 3, 2, "f16x2")
-    with pytest.raises(pc.CumulantError):
-        pc.Stream(6, 4, 2, "f16x2")
 
 
 def test_f16x2_scaling_extremes(dev, orc):

@@ -12,7 +12,7 @@ from errmeasure import e_d
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
+TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6, "f16x2": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -53,7 +53,7 @@ def check_window(orc, st, Xw, dmax, b, tol, exact=False):
             assert e <= tol, (d, e)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3", "f16x2"])
 def test_stream_equals_concatenation(dev, orc, prec):
     torch, pc = dev
     n, b, dmax = 13, 4, 5
@@ -68,7 +68,7 @@ def test_stream_equals_concatenation(dev, orc, prec):
     st.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16x2"])
 def test_stream_rolling_window(dev, orc, prec):
     """Add five batches, remove the first two: the cumulants of the last three."""
     torch, pc = dev
@@ -92,7 +92,7 @@ def test_stream_rolling_window(dev, orc, prec):
     st.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3", "f16x2"])
 def test_stream_integer_exact(dev, orc, prec):
     """Zero-sum small-integer batches with shift 0: the window's mean is 0 and
     every sum is exact, so the cumulants are bit-exact."""
@@ -172,7 +172,7 @@ def test_moebius_on_raw_moments(dev, orc, n, b, dmax):
     st.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3", "f16x2"])
 def test_moebius_integer_exact(dev, orc, prec):
     """Zero-mean small-integer data, t = 512, shift 0: every moment and every
     product of the formula is a short dyadic number, so the general formula
