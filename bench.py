@@ -634,6 +634,10 @@ def main():
         log(f"  slide of 2 x {sw['batch']} samples: {sw['ms_per_slide']:.3f} ms ({sw['samples_per_s'] / 1e6:.1f} M samples/s, "
             f"{sw['update_tflops']:.1f} TFLOP/s); cumulants {sw['cumulants_ms']['recursion']:.3f} ms (recursion), "
             f"{sw['cumulants_ms']['moebius']:.3f} ms (general formula)")
+        if main_p != "f16x2":
+            sw16 = bench_streaming(torch, pc, X, n, d_max, b, "f16x2", max(5, args.steps // 2))
+            line["streaming"]["other_precisions"] = {"f16x2": sw16}
+            log(f"  slide in f16x2: {sw16['ms_per_slide']:.3f} ms")
     if not args.no_workloads:
         line["workloads"] = bench_workloads(torch, pc, max(5, args.steps // 2), not args.no_tune)
         line["small"] = bench_small(torch, pc, max(50, args.steps * 5), not args.no_tune)
