@@ -91,8 +91,8 @@ typedef enum {
                     /* rounded to FP16 (22 bits of v), the 3 cross products    */
                     /* hh, hl, lh on FP16 matrix cores, FP32 sums over at most */
                     /* 64 samples, then FP64, the powers of two undone exactly */
-                    /* (orders 2..6; every call that centres its own data:     */
-                    /* cum_moment_blocks refuses it with CUM_EUNSUPPORTED)      */
+                    /* (orders 2..6; calls with d_max >= 7 that centre their   */
+                    /* own data stage in FP64 as for every prec)               */
     /* Not precisions: these give the enum the range of int32_t, so that an
      * unknown value is a valid cum_prec object that the library rejects with
      * CUM_EUNSUPPORTED (without them, reading one is undefined in C++). */
@@ -140,8 +140,9 @@ cum_status cum_center(const double *X, int64_t t, int n, int64_t ldx, cum_prec p
  *   Xc  t x n, leading dimension n, FP64 for CUM_F64, FP32 otherwise
  *   M   cum_layout.elems FP64 out
  * Requires t >= 1, 1 <= b <= n, 2 <= d <= CUM_MAX_ORDER.  Results are
- * deterministic: the same call gives bitwise the same output.  CUM_F16X2 is
- * refused (CUM_EUNSUPPORTED): its scaling needs the data's centring. */
+ * deterministic: the same call gives bitwise the same output.  With
+ * CUM_F16X2 (d <= 6, else CUM_EUNSUPPORTED) each variable is first divided
+ * by a power of two that brings its values, about zero, below 32. */
 cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, int d, int b, double *M, void *ws,
                              size_t ws_bytes, void *stream);
 

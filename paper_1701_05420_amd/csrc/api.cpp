@@ -1242,24 +1242,40 @@ cum_status cum_moment_blocks(const void *Xc, cum_prec prec, int64_t t, int n, in
                              size_t ws_bytes, void *stream) {
     cum_status st;
     if ((st = check_common(t, n, b)) || (st = check_prec(prec))) return st;
-    if (prec == CUM_F16X2)
-        return fail(CUM_EUNSUPPORTED, "the FP16 split scales the data it centres itself: use cum_cumulants");
     if (d < 2 || d > CUM_MAX_ORDER) return fail(CUM_EINVAL, "d must be in 2..%d", CUM_MAX_ORDER);
+    if (prec == CUM_F16X2 && d > 6)
+        return fail(CUM_EUNSUPPORTED, "the FP16 split contracts orders up to 6 (use CUM_F32 or CUM_F64)");
     if (!Xc || !M) return fail(CUM_EINVAL, "Xc and M must not be NULL");
     std::lock_guard<std::mutex> lk(g_mu);
     Call k;
     if ((st = get_call(n, b, d, d, prec, t, &k))) return st;
-    const size_t xbytes = staged_bytes(t, n, prec);
-    const size_t need = xbytes + align_up(partial_bytes(k));
+    int groups;
+    int64_t rows_per;
+    center_groups(t, groups, rows_per);
+    const size_t xbytes = staged_bytes(t, n, prec), pbytes = align_up(partial_bytes(k));
+    // FP16 split: each group's column sums (unused) beside its minima and maxima
+    const size_t cbytes = prec == CUM_F16X2 ? align_up((size_t)groups * n * 2 * 8) : 0;
+    const size_t need = xbytes + pbytes + cbytes + f16_bytes(prec, groups, n);
     if (!ws || ws_bytes < need) return fail(CUM_ENOMEM, "moment_blocks needs %zu workspace bytes", need);
     if ((st = upload_call(k))) return st;
     hipStream_t s = (hipStream_t)stream;
     char *Xst = (char *)ws;
+    const double *scale = nullptr;
+    if (prec == CUM_F16X2) {
+        // the data as given, each variable divided by a power of two bounding it
+        // about zero; undone in the contraction
+        char *cw = Xst + xbytes + pbytes, *fw = cw + cbytes;
+        double *mm = (double *)fw, *sc = (double *)(fw + align_up((size_t)groups * n * 2 * 8));
+        HIP_TRY(timed(CUM_KIND_CENTER, s, [&] {
+            return launch_scale_f32((const float *)Xc, t, n, rows_per, groups, (double *)cw, mm, sc, s);
+        }));
+        scale = sc;
+    }
     HIP_TRY(timed(CUM_KIND_CENTER, s, [&] {
-        return launch_stage(Xc, t, n, n, nullptr, Xst, prec, false, prec == CUM_F64, s);
+        return launch_stage(Xc, t, n, n, nullptr, Xst, prec, false, prec == CUM_F64, s, scale);
     }));
     double *outs[1] = {M};
-    return run_orders(k, Xst, (double *)(Xst + xbytes), outs, false, s);
+    return run_orders(k, Xst, (double *)(Xst + xbytes), outs, false, s, nullptr, scale);
 }
 
 static_assert(NOALLOC_SCRATCH_BYTES == CUM_NOALLOC_SCRATCH_BYTES, "scratch size");

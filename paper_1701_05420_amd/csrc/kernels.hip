@@ -59,8 +59,8 @@ __device__ __forceinline__ int64_t ipow_dev(int b, int e) {
 // Neumaier-compensated; then x - mean in FP64, stored in the device precision.
 // ---------------------------------------------------------------------------
 // MM: also each column's minimum and maximum over the group (mm)
-template <bool MM = false>
-__device__ __forceinline__ void colsum_body(const double *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int g,
+template <bool MM = false, typename TI = double>
+__device__ __forceinline__ void colsum_body(const TI *X, int64_t t, int n, int64_t ldx, int64_t rows_per, int g,
                                             double *part, double *mm = nullptr) {
     __shared__ double ss[256], cs[256];
     __shared__ double lo_s[MM ? 256 : 1], hi_s[MM ? 256 : 1];
@@ -76,7 +76,7 @@ __device__ __forceinline__ void colsum_body(const double *X, int64_t t, int n, i
         for (; r + 7 * R < r1; r += 8 * R) {
             double x[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = X[(r + u * R) * ldx + col];
+            for (int u = 0; u < 8; ++u) x[u] = (double)X[(r + u * R) * ldx + col];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 neumaier(s, c, x[u]);
@@ -87,7 +87,7 @@ __device__ __forceinline__ void colsum_body(const double *X, int64_t t, int n, i
             }
         }
         for (; r < r1; r += R) {
-            const double x = X[r * ldx + col];
+            const double x = (double)X[r * ldx + col];
             neumaier(s, c, x);
             if constexpr (MM) {
                 lo = fmin(lo, x);
@@ -129,6 +129,15 @@ __global__ __launch_bounds__(256) void colsum_kernel(const double *X, int64_t t,
 
 // One work-group per column: thread k sums groups k, k+256, ...; the 256
 // compensated partials are then combined pairwise in a fixed tree.
+// The FP16 split's power of two for values in [lo, hi] staged about c:
+// 2^(e - 5), where a = max |x - c| lies in [2^(e-1), 2^e) (1 where a = 0).
+__device__ __forceinline__ double f16_scale(double lo, double hi, double c) {
+    const double a = fmax(hi - c, c - lo);
+    int e = 0;
+    if (a > 0.0) (void)frexp(a, &e);  // a = f * 2^e, f in [0.5, 1): 2^e > a
+    return a > 0.0 ? ldexp(1.0, e - 5) : 1.0;
+}
+
 // MM (the FP16 split): from the groups' minima and maxima, also the power of
 // two scale[i] = 2^(e - 5), where a = max |x - c| over the column lies in
 // [2^(e-1), 2^e), c being center[i] if given (the fixed shift a stream stages
@@ -176,15 +185,40 @@ __device__ __forceinline__ void mean_body(const double *part, int groups, int n,
         mean[i] = mu;
         if constexpr (MM) {
             // the values are staged about center (a stream's fixed shift) when given
-            const double c = center ? center[i] : mu;
-            const double a = fmax(hi_s[0] - c, c - lo_s[0]);
-            int e = 0;
-            if (a > 0.0) {
-                (void)frexp(a, &e);  // a = f * 2^e, f in [0.5, 1): 2^e >= a
-            }
-            scale[i] = a > 0.0 ? ldexp(1.0, e - 5) : 1.0;
+            scale[i] = f16_scale(lo_s[0], hi_s[0], center ? center[i] : mu);
             if (i == 0) scale[n] = 1.0;
         }
+    }
+}
+
+// The FP16 split of FP32 data taken as given (cum_moment_blocks): each
+// group's column sums (unused) and minima / maxima, then per column the
+// power of two bounding the values about zero.
+__global__ __launch_bounds__(256) void colminmax_f32_kernel(const float *X, int64_t t, int n, int64_t rows_per,
+                                                            double *part, double *mm) {
+    colsum_body<true, float>(X, t, n, n, rows_per, blockIdx.x, part, mm);
+}
+
+__global__ __launch_bounds__(256) void scale_about_zero_kernel(const double *mm, int groups, int n, double *scale) {
+    __shared__ double lo_s[256], hi_s[256];
+    const int tid = threadIdx.x, i = blockIdx.x;
+    double L = INFINITY, H = -INFINITY;
+    for (int g = tid; g < groups; g += 256) {
+        L = fmin(L, mm[((int64_t)g * n + i) * 2]);
+        H = fmax(H, mm[((int64_t)g * n + i) * 2 + 1]);
+    }
+    lo_s[tid] = L;
+    hi_s[tid] = H;
+    for (int w = 128; w > 0; w >>= 1) {
+        __syncthreads();
+        if (tid < w) {
+            lo_s[tid] = fmin(lo_s[tid], lo_s[tid + w]);
+            hi_s[tid] = fmax(hi_s[tid], hi_s[tid + w]);
+        }
+    }
+    if (tid == 0) {
+        scale[i] = f16_scale(lo_s[0], hi_s[0], 0.0);
+        if (i == 0) scale[n] = 1.0;
     }
 }
 
@@ -270,11 +304,24 @@ __global__ __launch_bounds__(256) void stage_scaled_kernel(const double *X, int6
         stage_body<double, float, true, true>(X, t, n, ldx, mean, Xst, KT, KTP, s, scale);
 }
 
+// FP32 data taken as given, divided by per-variable powers of two (FP16 split)
+__global__ __launch_bounds__(256) void stage_scaled_f32_kernel(const float *X, int64_t t, int n, int64_t ldx,
+                                                               const double *scale, float *Xst, int KT, int KTP,
+                                                               int64_t nstages) {
+    for (int64_t s = blockIdx.x; s < nstages; s += gridDim.x)
+        stage_body<float, float, false, true>(X, t, n, ldx, nullptr, Xst, KT, KTP, s, scale);
+}
+
 hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xst, int prec,
                         bool center, bool in_f64, hipStream_t s, const double *scale) {
     const int KT = stage_kt(prec), KTP = stage_pitch(prec);
     const int64_t nst = (t + KT - 1) / KT;
     const unsigned grid = (unsigned)std::min<int64_t>(nst, 65535);
+    if (scale && !center && !in_f64 && prec != P_F64) {
+        hipLaunchKernelGGL(stage_scaled_f32_kernel, dim3(grid), dim3(256), 0, s, (const float *)X, t, n, ldx, scale,
+                           (float *)Xst, KT, KTP, nst);
+        return hipGetLastError();
+    }
     if (scale) {
         if (!center || !in_f64 || prec == P_F64) return hipErrorInvalidValue;
         hipLaunchKernelGGL(stage_scaled_kernel, dim3(grid), dim3(256), 0, s, (const double *)X, t, n, ldx, mean, scale,
@@ -2236,6 +2283,13 @@ hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t
         hipLaunchKernelGGL(colsum_kernel<true>, dim3(groups), dim3(256), 0, s, X, t, n, ldx, rows_per, part, mm);
     else
         hipLaunchKernelGGL(colsum_kernel<false>, dim3(groups), dim3(256), 0, s, X, t, n, ldx, rows_per, part, mm);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_f32(const float *X, int64_t t, int n, int64_t rows_per, int groups, double *part, double *mm,
+                            double *scale, hipStream_t s) {
+    hipLaunchKernelGGL(colminmax_f32_kernel, dim3(groups), dim3(256), 0, s, X, t, n, rows_per, part, mm);
+    hipLaunchKernelGGL(scale_about_zero_kernel, dim3(n), dim3(256), 0, s, mm, groups, n, scale);
     return hipGetLastError();
 }
 

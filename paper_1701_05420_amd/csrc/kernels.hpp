@@ -80,7 +80,8 @@ enum TileShape { TS_1x1 = 0, TS_1x2 = 2 };
 
 int lds_bytes_moment(int prec, int n);
 // row-major data (FP64 with ldx, or FP32 with ldx) -> staged layout, optionally centred;
-// with scale (FP16 split, centred FP64 input only), variable v is divided by scale[v]
+// with scale (FP16 split: centred FP64 input, or FP32 input taken as given),
+// variable v is divided by scale[v]
 hipError_t launch_stage(const void *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xst, int prec,
                         bool center, bool in_f64, hipStream_t s, const double *scale = nullptr);
 hipError_t launch_moment(int prec, int shape, int dmax, const MomentArgs &a, int grid, hipStream_t s);
@@ -106,6 +107,12 @@ hipError_t launch_colsum(const double *X, int64_t t, int n, int64_t ldx, int64_t
                          hipStream_t s, double *mm = nullptr);
 hipError_t launch_mean(const double *part, int groups, int n, int64_t t, double *mean, hipStream_t s,
                        const double *mm = nullptr, double *scale = nullptr, const double *center = nullptr);
+// FP16 split of FP32 data taken as given (t x n, ld n): each group's column
+// sums (part) and minima / maxima (mm, groups x n x 2 each), then scale
+// (n + 1): per variable the power of two bounding its values about zero below
+// 32 (see mean_body), and scale[n] = 1.
+hipError_t launch_scale_f32(const float *X, int64_t t, int n, int64_t rows_per, int groups, double *part, double *mm,
+                            double *scale, hipStream_t s);
 hipError_t launch_center(const double *X, int64_t t, int n, int64_t ldx, const double *mean, void *Xc, int prec,
                          hipStream_t s);
 hipError_t launch_unfold(const double *blocks, int n, int d, int b, double *dense, hipStream_t s);

@@ -11,8 +11,8 @@ entries of order d):
     data amplify), and bit-exact on small-integer data;
   * FP16x2 path (FP16 hi and 2^11-scaled lo, 22 bits per operand, after a
     per-variable power-of-two scaling): 1e-6, and bit-exact on small-integer
-    data.  Orders up to 6 (from order 7 on every call stages in FP64); every
-    call that centres its own data takes it, moment_blocks refuses it.
+    data.  Orders up to 6 (from order 7 on the calls that centre their own
+    data stage in FP64, and moment_blocks refuses it).
 """
 import sys
 
@@ -150,7 +150,7 @@ def test_ragged_small_dense(dev, orc, prec, n, b, t, dmax):
         assert e <= TOL[prec], (d, e)
 
 
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", CPRECS)
 def test_moment_blocks_multi_tile_sampled(dev, orc, prec):
     """n = 37, b = 5: several work-group tiles per order and a ragged block."""
     torch, pc = dev
@@ -179,13 +179,14 @@ def test_moment_blocks_multi_tile_sampled(dev, orc, prec):
             assert not np.any(M[all_offs[~real]])
 
 
-def test_f16x2_refused_outside_cumulants(dev):
-    """The FP16 split scales the data it centres itself, so the call that takes
-    centred data refuses it (CUM_EUNSUPPORTED)."""
+def test_f16x2_moment_blocks_orders(dev):
+    """cum_moment_blocks contracts the data it is given in the precision asked
+    for, and the FP16 split holds orders up to 6 only (CUM_EUNSUPPORTED)."""
     torch, pc = dev
-    Xd = torch.from_numpy(workloads.t_gamma_mix(t=1000, n=6, seed=2)).cuda()
+    Xd = torch.from_numpy(workloads.t_gamma_mix(t=1000, n=6, seed=2)).cuda().float()
+    assert pc.moment_blocks(Xd, 6, 2, "f16x2").shape[0] == pc.layout(6, 6, 2)["elems"]
     with pytest.raises(pc.CumulantError):
-        pc.moment_blocks(Xd.float(), 3, 2, "f16x2")
+        pc.moment_blocks(Xd, 7, 2, "f16x2")
 
 
 def test_f16x2_scaling_extremes(dev, orc):
