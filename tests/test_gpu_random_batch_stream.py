@@ -18,7 +18,7 @@ from errmeasure import bound, e_d
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
+TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6, "f16x2": 1e-6}
 PRECS = ["f64", "f32", "bf16x2", "bf16x3"]
 
 
@@ -54,7 +54,7 @@ def check(orc, X, mean, K, d_max, b, tol, prec, shift=None):
         assert e <= tl, (d, e, tl)
 
 
-def batch_cases(count=10, seed=17010):
+def batch_cases(count=10, seed=17010, precs=None):
     rng = np.random.default_rng(seed)
     out = []
     while len(out) < count:
@@ -65,11 +65,12 @@ def batch_cases(count=10, seed=17010):
         b = int(rng.integers(1, n + 1))
         sets = int(rng.integers(1, 13))
         ts = [int(x) for x in rng.choice([1, 2, 3, 63, 64, 65, 300, 1000, 2500], size=sets)]
-        out.append((n, b, d_max, PRECS[int(rng.integers(0, 4))], ts, int(rng.integers(1 << 30))))
+        prec = PRECS[int(rng.integers(0, 4))] if precs is None else precs[int(rng.integers(0, len(precs)))]
+        out.append((n, b, d_max, prec, ts, int(rng.integers(1 << 30))))
     return out
 
 
-@pytest.mark.parametrize("n,b,d_max,prec,ts,seed", batch_cases())
+@pytest.mark.parametrize("n,b,d_max,prec,ts,seed", batch_cases() + batch_cases(count=5, seed=17016, precs=["f16x2"]))
 def test_random_batch(dev, orc, n, b, d_max, prec, ts, seed):
     torch, pc = dev
     say(f"batch n={n} b={b} d_max={d_max} prec={prec} t={ts}")
@@ -84,7 +85,7 @@ def test_random_batch(dev, orc, n, b, d_max, prec, ts, seed):
         batch.close()
 
 
-def stream_cases(count=10, seed=17011):
+def stream_cases(count=10, seed=17011, precs=None):
     rng = np.random.default_rng(seed)
     out = []
     while len(out) < count:
@@ -95,12 +96,15 @@ def stream_cases(count=10, seed=17011):
         b = int(rng.integers(1, n + 1))
         method = ["recursion", "moebius"][int(rng.integers(0, 2))]
         # the general formula subtracts products of raw moments: FP64 only here
-        prec = "f64" if method == "moebius" else PRECS[int(rng.integers(0, 4))]
+        if method == "moebius":
+            prec = "f64"
+        else:
+            prec = PRECS[int(rng.integers(0, 4))] if precs is None else precs[int(rng.integers(0, len(precs)))]
         out.append((n, b, d_max, prec, method, int(rng.integers(1 << 30))))
     return out
 
 
-@pytest.mark.parametrize("n,b,d_max,prec,method,seed", stream_cases())
+@pytest.mark.parametrize("n,b,d_max,prec,method,seed", stream_cases() + stream_cases(count=5, seed=17017, precs=["f16x2"]))
 def test_random_stream_sequence(dev, orc, n, b, d_max, prec, method, seed):
     """Twelve random adds and removes about a fixed shift near the data's
     mean; the window is checked after the sixth and the last operation."""
